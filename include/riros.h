@@ -1,0 +1,173 @@
+/*
+ * riros.h -- C interface of the MI355X word-level RTL fault simulator.
+ *
+ * The simulator runs many faulty copies of a word-level RTL design cycle by
+ * cycle against a golden (fault-free) trace and reports, for every injected
+ * single stuck-at fault, the first cycle in which any primary output differs
+ * from the golden value, or that the fault stayed undetected (paper, Sec. II-B:
+ * a fault is injected, the faulty machine is simulated, and the fault is
+ * detected by comparing faulty against good values).  Faults on wires sit on
+ * the node that drives the wire, faults on registers on the register's node
+ * (Sec. IV-A, unified fault injection).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: RIROS_OK (0) on success, a negative RIROS_E* code on
+ *     failure; riros_last_error() then returns a message (thread-local).  On
+ *     failure no output buffer has been written.
+ *   - Every input array is owned by the caller and is only read during the
+ *     call.  Handles are owned by the library until the matching riros_free_*.
+ *   - `stream` arguments are a hipStream_t owned by the caller, or NULL for
+ *     the null stream.  Host-side outputs are complete when the call returns.
+ *   - Values are two-state and unsigned; each node's value is kept masked to
+ *     its width (1..64 bits).
+ */
+#ifndef RIROS_H
+#define RIROS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RIROS_OK 0
+#define RIROS_EINVAL (-1)   /* malformed design, fault, option or argument */
+#define RIROS_ECYCLE (-2)   /* combinational loop (a cycle not cut by a register) */
+#define RIROS_ENOMEM (-3)   /* host or device allocation failed */
+#define RIROS_EDEVICE (-4)  /* HIP runtime error */
+
+#define RIROS_UNDETECTED 0xFFFFFFFFu
+
+/* Node operators.  Operands are zero-extended, results masked to the width.
+ *   CONST  value = param
+ *   PI     value = stimulus[t][param]
+ *   REG    value = state; state(0) = param, state(t+1) = value(in[0], t)
+ *          (end-of-cycle update of non-blocking assignments, Sec. II-B);
+ *          in[0] must have the register's width
+ *   ADD SUB AND OR XOR MUL            in[0] op in[1] (ADD/SUB/MUL modulo 2^width)
+ *   NOT                                ~in[0]
+ *   MUX                                in[0] != 0 ? in[2] : in[1]
+ *   SHL SHR                            in[0] << param, in[0] >> param (logical)
+ *   EQ NE ULT                          in[0] == / != / < in[1], as 0 or 1
+ *   SLICE                              in[0] >> param
+ *   CONCAT                             (in[0] << width(in[1])) | in[1]       */
+enum {
+    RIROS_OP_CONST = 0, RIROS_OP_PI, RIROS_OP_REG, RIROS_OP_ADD, RIROS_OP_SUB,
+    RIROS_OP_AND, RIROS_OP_OR, RIROS_OP_XOR, RIROS_OP_NOT, RIROS_OP_MUX,
+    RIROS_OP_SHL, RIROS_OP_SHR, RIROS_OP_EQ, RIROS_OP_NE, RIROS_OP_ULT,
+    RIROS_OP_SLICE, RIROS_OP_CONCAT, RIROS_OP_MUL, RIROS_NUM_OPS
+};
+
+/* One RTL node (24 bytes).  Operand slots a node's operator does not read are
+ * ignored.  Node ids are indexes into the node array. */
+typedef struct {
+    uint8_t op;
+    uint8_t width;       /* 1..64 */
+    uint16_t reserved;
+    uint32_t in[3];      /* operand node ids */
+    uint64_t param;      /* CONST value, PI column, REG reset value, shift amount or SLICE low bit */
+} riros_node;
+
+/* A single stuck-at fault: bit `bit` of node `site` is forced to `stuck` in
+ * every cycle (the forcing applies to the node's value as seen by its users
+ * and by output comparison; a register's next-state write is not forced). */
+typedef struct {
+    uint32_t site;
+    uint8_t bit;         /* < width(site) */
+    uint8_t stuck;       /* 0 or 1 */
+    uint16_t reserved;
+} riros_fault;
+
+typedef struct {
+    uint32_t num_nodes;
+    const riros_node* nodes;
+    uint32_t num_pi;     /* stimulus columns; every PI's param is < num_pi */
+    uint32_t num_po;
+    const uint32_t* po;  /* primary-output node ids */
+} riros_design_desc;
+
+typedef struct riros_design_s* riros_design;
+typedef struct riros_golden_s* riros_golden;
+
+/* Validate a design, levelise it (registers cut every combinational cycle) and
+ * upload its levelised image to the current HIP device.  This is the compile
+ * step that turns RTL into a graph of nodes and the node graph into schedulable
+ * work (Sec. IV, Steps 1 and 4).  Errors: RIROS_EINVAL for a bad operator,
+ * width, operand id, PI column, PO id or a register whose D input has another
+ * width; RIROS_ECYCLE for a combinational loop; RIROS_ENOMEM; RIROS_EDEVICE.
+ * On success *out is a new handle (free with riros_free_design). */
+int riros_load_design(const riros_design_desc* desc, riros_design* out);
+void riros_free_design(riros_design d);
+
+/* Simulate the fault-free machine for cycles 0..T-1 and keep the golden trace
+ * resident in device memory (the "good gate" values every bad gate is compared
+ * against, Sec. II-B).  `stimulus` is a host array uint64[T][num_pi], row t =
+ * primary-input values of cycle t (masked to each PI's width on use).  The
+ * trace takes 8*T*num_nodes bytes of device memory.  Errors: RIROS_EINVAL
+ * (T == 0, NULL pointers), RIROS_ENOMEM, RIROS_EDEVICE.  *out is a new handle. */
+int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream,
+                     riros_golden* out);
+void riros_free_golden(riros_golden g);
+
+/* Copy cycles [t0, t0+nt) of a golden trace to host memory as
+ * uint64[nt][num_nodes], in the caller's node numbering. */
+int riros_golden_read(riros_golden g, uint32_t t0, uint32_t nt, uint64_t* out);
+
+/* Scheduling mode of riros_fault_sim. */
+#define RIROS_MODE_PLAIN 0     /* one fault per wavefront, static fault order */
+#define RIROS_MODE_TWO_D 1     /* light faults one per lane, heavy faults split
+                                  structurally; persistent work queue */
+
+typedef struct {
+    int32_t mode;          /* RIROS_MODE_* */
+    int32_t drop;          /* 1: stop a fault at its detect cycle; 0: run all T cycles */
+    int32_t io_on_device;  /* 1: faults, detect, events and coverage are device pointers
+                              and the call is asynchronous on `stream` */
+    int32_t waves_per_cu;  /* resident wavefronts per compute unit (0 = default) */
+    const float* priority; /* optional per-fault predicted load (device pointer when
+                              io_on_device, else host); higher runs first.  Only
+                              changes the schedule, never a result */
+    float theta;           /* TWO_D: priority above which a fault starts on the
+                              structural (heavy) path; +inf = all light */
+    int32_t light_cap;     /* TWO_D: per-lane divergent-node capacity (0 = default);
+                              a lane that overflows is moved to the heavy path */
+    int32_t chunk;         /* TWO_D: faults taken per queue pop (0 = default) */
+    void* stream;
+} riros_sim_opts;
+
+typedef struct {
+    uint64_t detected;      /* faults with a detect cycle */
+    uint64_t total;         /* faults simulated */
+    uint64_t fault_cycles;  /* sum over faults of (detect + 1), or T if undetected */
+    uint64_t events;        /* sum of per-fault event counts */
+} riros_coverage;
+
+/* Fault-simulate F single stuck-at faults against the golden trace.
+ * detect[F] receives the first cycle in which any primary output of the
+ * faulty machine differs from the golden trace, or RIROS_UNDETECTED.
+ * events[F] (may be NULL) receives the fault's bad-gate evaluations: node n in
+ * cycle t counts when one of its inputs (for a register: its state) or its own
+ * value differs from the golden machine (Sec. II-B, concurrent fault
+ * simulation); with drop = 1 the count stops after the detect cycle.
+ * cov (may be NULL) receives totals.  Results do not depend on mode, priority,
+ * theta, chunk or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
+ * bit >= width, stuck > 1, unknown mode, design/golden mismatch), RIROS_ENOMEM,
+ * RIROS_EDEVICE. */
+int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
+                    const riros_sim_opts* opts, uint32_t* detect, uint64_t* events,
+                    riros_coverage* cov);
+
+/* Number of nodes, levels and registers of a loaded design. */
+int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels, uint32_t* num_regs);
+
+/* Duration in milliseconds of the fault-simulation kernels of the last
+ * riros_fault_sim call on this thread (HIP events on its stream; the call must
+ * have completed). */
+int riros_last_kernel_ms(float* ms);
+
+const char* riros_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIROS_H */

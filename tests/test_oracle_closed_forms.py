@@ -1,0 +1,141 @@
+"""Pin the oracle's fault simulation on designs whose detect cycles have closed forms."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from bitblast import simulate
+from helpers import Builder, all_faults, faults
+from paper_2508_16376_amd.workloads import ADD, AND, CONST, OR, REG, XOR, MUX, counter_values
+
+UND = oracle.UNDETECTED
+
+
+def counter(n, po_is_adder=False):
+    """n-bit counter: cnt' = cnt + 1 from reset 0; golden cnt(t) = t mod 2^n."""
+    b = Builder()
+    x = b.pi(1)                      # unused input, keeps the stimulus non-empty
+    cnt = b.reg(n)
+    one = b.const(n, 1)
+    add = b.node(ADD, n, (cnt, one))
+    b.set_d(cnt, add)
+    d = b.design([add if po_is_adder else cnt])
+    return d, cnt, add, x
+
+
+@pytest.mark.parametrize("n", [3, 6, 10])
+def test_counter_golden_trace(n):
+    d, cnt, add, _ = counter(n)
+    T = 3000
+    G = oracle.golden(d, np.zeros((T, 1), dtype=np.uint64), T)
+    t = np.arange(T, dtype=np.uint64)
+    np.testing.assert_array_equal(G[:, cnt], t % np.uint64(1 << n))
+    np.testing.assert_array_equal(G[:, add], (t + np.uint64(1)) % np.uint64(1 << n))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("drop", [True, False])
+def test_counter_register_faults(variant, drop):
+    n, T = 10, 600
+    d, cnt, add, _ = counter(n)
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    fl = faults([(cnt, k, 0) for k in range(n)] + [(cnt, k, 1) for k in range(n)])
+    det, ev = oracle.fault_sim(d, stim, T, fl, drop=drop, variant=variant)
+    for k in range(n):
+        # SA0 on bit k: the state first has bit k set at t = 2^k
+        assert det[k] == (2 ** k if 2 ** k < T else UND), k
+        # SA1 on bit k: the reset state 0 already differs
+        assert det[n + k] == 0
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_counter_adder_faults(variant):
+    n, T = 9, 700
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    for po_is_adder in (False, True):
+        d, cnt, add, _ = counter(n, po_is_adder)
+        fl = faults([(add, k, 0) for k in range(n)] + [(add, k, 1) for k in range(n)])
+        det, _ = oracle.fault_sim(d, stim, T, fl, variant=variant)
+        for k in range(n):
+            # SA0: the adder output t+1 first has bit k set at t = 2^k - 1
+            first = 2 ** k - 1 + (0 if po_is_adder else 1)
+            assert det[k] == (first if first < T else UND), (po_is_adder, k)
+            # SA1: excited at t = 0 for k >= 1 (1 has bit k clear), at t = 1 for k = 0
+            first1 = (0 if k >= 1 else 1) + (0 if po_is_adder else 1)
+            assert det[n + k] == first1, (po_is_adder, k)
+
+
+def delay_line(L, w):
+    b = Builder()
+    x = b.pi(w)
+    regs = [b.reg(w) for _ in range(L)]
+    b.set_d(regs[0], x)
+    for j in range(1, L):
+        b.set_d(regs[j], regs[j - 1])
+    return b.design([regs[-1]]), x, regs
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_delay_line(variant):
+    L, w, T = 5, 4, 200
+    d, x, regs = delay_line(L, w)
+    stim = (counter_values(77, 0, T) & np.uint64(15))[:, None]
+    po_golden = np.zeros(T, dtype=np.uint64)
+    po_golden[L:] = stim[:T - L, 0]
+    rows = [(regs[j], b, v) for j in range(L) for b in range(w) for v in (0, 1)]
+    det, _ = oracle.fault_sim(d, stim, T, faults(rows), variant=variant)
+    G = oracle.golden(d, stim, T)
+    np.testing.assert_array_equal(G[:, regs[-1]], po_golden)
+    for i, (site, b, v) in enumerate(rows):
+        j = regs.index(site) + 1                   # stage number 1..L
+        bits = (po_golden >> np.uint64(b)) & np.uint64(1)
+        cand = [t for t in range(L - j, T) if int(bits[t]) != v]
+        assert det[i] == (cand[0] if cand else UND), (j, b, v)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_po_node_fault_is_first_excitation(variant):
+    """A fault on a primary output's own node is detected at its first excitation,
+    also when the output feeds back through registers."""
+    b = Builder()
+    a = b.pi(8)
+    r = b.reg(8)
+    s = b.node(XOR, 8, (a, r))
+    b.set_d(r, s)
+    d = b.design([s])
+    T = 300
+    stim = (counter_values(5, 0, T) & np.uint64(255))[:, None]
+    fl = all_faults(d, [s])
+    det, _ = oracle.fault_sim(d, stim, T, fl, variant=variant)
+    G = oracle.golden(d, stim, T)
+    for i in range(fl.size):
+        bit = (G[:, s] >> np.uint64(fl["bit"][i])) & np.uint64(1)
+        exc = np.nonzero(bit != fl["stuck"][i])[0]
+        assert det[i] == (exc[0] if exc.size else UND)
+
+
+def test_combinational_exhaustive_first_distinguishing_vector():
+    """Purely combinational design, stimulus t = t-th input vector: the detect
+    cycle is the index of the first vector on which faulty and good outputs differ
+    (computed with the gate-level evaluator)."""
+    b = Builder()
+    p = [b.pi(2) for _ in range(3)]
+    n1 = b.node(ADD, 2, (p[0], p[1]))
+    n2 = b.node(AND, 2, (n1, p[2]))
+    n3 = b.node(XOR, 2, (n1, p[1]))
+    n4 = b.node(MUX, 2, (b.node(XOR, 1, (n2, n3)), n2, n3))
+    n5 = b.node(OR, 1, (n4, p[0]))
+    d = b.design([n4, n5])
+    vecs = np.array(list(itertools.product(range(4), repeat=3)), dtype=np.uint64)
+    T = vecs.shape[0]
+    fl = all_faults(d, [n for n in range(d.num_nodes)])
+    for variant in (0, 1):
+        det, _ = oracle.fault_sim(d, vecs, T, fl, variant=variant)
+        for i in range(fl.size):
+            f = (int(fl["site"][i]), int(fl["bit"][i]), int(fl["stuck"][i]))
+            good = simulate(d, vecs[:, None, :])[:, 0, :]
+            bad = simulate(d, vecs[:, None, :], f)[:, 0, :]
+            diff = (good[:, d.po] != bad[:, d.po]).any(axis=1)
+            want = int(np.argmax(diff)) if diff.any() else UND
+            assert det[i] == want, (variant, f)
