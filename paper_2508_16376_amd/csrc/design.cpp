@@ -1,0 +1,202 @@
+// Design compiler: turns the caller's node list into the levelised image the
+// kernels use.  The paper compiles RTL into a graph of RTL nodes and maps the
+// graph one-to-one onto tasks (Sec. IV, Steps 1 and 4); here the graph is
+// validated, cut at registers, levelised (level 0 = registers, inputs,
+// constants; a combinational node sits one level above its deepest operand)
+// and renumbered level by level so that each level is a contiguous id range.
+#include "design.hpp"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace riros {
+
+int op_arity(uint8_t op)
+{
+    switch (op) {
+    case RIROS_OP_CONST: case RIROS_OP_PI: return 0;
+    case RIROS_OP_REG: case RIROS_OP_NOT: case RIROS_OP_SHL: case RIROS_OP_SHR:
+    case RIROS_OP_SLICE: return 1;
+    case RIROS_OP_MUX: return 3;
+    default: return 2;
+    }
+}
+
+bool op_is_comb(uint8_t op)
+{
+    return op != RIROS_OP_CONST && op != RIROS_OP_PI && op != RIROS_OP_REG;
+}
+
+static int fail(std::string& err, int code, const char* fmt, unsigned a = 0, unsigned b = 0)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, fmt, a, b);
+    err = buf;
+    return code;
+}
+
+int build_image(const riros_design_desc& d, Image& img, std::string& err)
+{
+    const uint32_t N = d.num_nodes;
+    if (N == 0 || d.nodes == nullptr) return fail(err, RIROS_EINVAL, "design has no nodes");
+    if (N >= 0x7FFFFFFFu) return fail(err, RIROS_EINVAL, "too many nodes");
+    if (d.num_po > 0 && d.po == nullptr) return fail(err, RIROS_EINVAL, "po is NULL");
+    const riros_node* nd = d.nodes;
+    for (uint32_t n = 0; n < N; ++n) {
+        const riros_node& x = nd[n];
+        if (x.op >= RIROS_NUM_OPS) return fail(err, RIROS_EINVAL, "node %u: unknown operator %u", n, x.op);
+        if (x.width < 1 || x.width > 64) return fail(err, RIROS_EINVAL, "node %u: width %u not in 1..64", n, x.width);
+        for (int k = 0; k < op_arity(x.op); ++k)
+            if (x.in[k] >= N) return fail(err, RIROS_EINVAL, "node %u: operand id %u out of range", n, x.in[k]);
+        if (x.op == RIROS_OP_PI && x.param >= d.num_pi)
+            return fail(err, RIROS_EINVAL, "node %u: PI column %u >= num_pi", n, (unsigned)x.param);
+        if (x.op == RIROS_OP_REG && nd[x.in[0]].width != x.width)
+            return fail(err, RIROS_EINVAL, "register %u: D input width %u differs", n, nd[x.in[0]].width);
+    }
+    for (uint32_t i = 0; i < d.num_po; ++i)
+        if (d.po[i] >= N) return fail(err, RIROS_EINVAL, "po[%u] = %u out of range", i, d.po[i]);
+
+    // Levels by Kahn's algorithm over combinational edges.
+    std::vector<uint32_t> indeg(N, 0), uoff(N + 1, 0), lvl(N, 0);
+    for (uint32_t n = 0; n < N; ++n)
+        if (op_is_comb(nd[n].op))
+            for (int k = 0; k < op_arity(nd[n].op); ++k) { uoff[nd[n].in[k] + 1]++; indeg[n]++; }
+    for (uint32_t n = 0; n < N; ++n) uoff[n + 1] += uoff[n];
+    std::vector<uint32_t> users(uoff[N]), fill(N, 0);
+    for (uint32_t n = 0; n < N; ++n)
+        if (op_is_comb(nd[n].op))
+            for (int k = 0; k < op_arity(nd[n].op); ++k) {
+                uint32_t s = nd[n].in[k];
+                users[uoff[s] + fill[s]++] = n;
+            }
+    std::vector<uint32_t> q;
+    q.reserve(N);
+    for (uint32_t n = 0; n < N; ++n)
+        if (indeg[n] == 0) q.push_back(n);
+    for (size_t h = 0; h < q.size(); ++h) {
+        uint32_t s = q[h];
+        for (uint32_t e = uoff[s]; e < uoff[s + 1]; ++e) {
+            uint32_t u = users[e];
+            lvl[u] = std::max(lvl[u], lvl[s] + 1);
+            if (--indeg[u] == 0) q.push_back(u);
+        }
+    }
+    if (q.size() != N) return fail(err, RIROS_ECYCLE, "combinational loop through %u nodes", (unsigned)(N - q.size()));
+
+    uint32_t L = 0;
+    for (uint32_t n = 0; n < N; ++n) L = std::max(L, lvl[n] + 1);
+
+    // Level-major numbering; inside level 0 registers come first.
+    auto rank = [&](uint32_t n) -> uint32_t {
+        if (lvl[n] != 0) return 3;
+        return nd[n].op == RIROS_OP_REG ? 0 : (nd[n].op == RIROS_OP_PI ? 1 : 2);
+    };
+    std::vector<uint32_t> order(N);
+    for (uint32_t n = 0; n < N; ++n) order[n] = n;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (lvl[a] != lvl[b]) return lvl[a] < lvl[b];
+        return rank(a) < rank(b);
+    });
+    img.N = N;
+    img.L = L;
+    img.npi = d.num_pi;
+    img.u2i.assign(N, 0);
+    img.i2u = order;
+    for (uint32_t i = 0; i < N; ++i) img.u2i[order[i]] = i;
+    img.R = 0;
+    for (uint32_t n = 0; n < N; ++n) img.R += nd[n].op == RIROS_OP_REG;
+    img.lvl_off.assign(L + 1, 0);
+    img.level.assign(N, 0);
+    for (uint32_t i = 0; i < N; ++i) {
+        img.level[i] = lvl[order[i]];
+        img.lvl_off[img.level[i] + 1]++;
+    }
+    for (uint32_t l = 0; l < L; ++l) img.lvl_off[l + 1] += img.lvl_off[l];
+
+    img.desc.assign(N, Desc{});
+    for (uint32_t i = 0; i < N; ++i) {
+        const riros_node& x = nd[order[i]];
+        Desc& o = img.desc[i];
+        o.op = x.op;
+        o.width = x.width;
+        uint64_t m = x.width >= 64 ? ~0ull : ((1ull << x.width) - 1);
+        switch (x.op) {
+        case RIROS_OP_CONST:
+            o.a = (uint32_t)(x.param & m);
+            o.b = (uint32_t)((x.param & m) >> 32);
+            break;
+        case RIROS_OP_PI:
+            o.a = (uint32_t)x.param;
+            break;
+        case RIROS_OP_REG:
+            o.a = img.u2i[x.in[0]];
+            o.b = (uint32_t)(x.param & m);
+            o.c = (uint32_t)((x.param & m) >> 32);
+            break;
+        case RIROS_OP_SHL: case RIROS_OP_SHR: case RIROS_OP_SLICE:
+            o.a = img.u2i[x.in[0]];
+            o.b = x.param >= 64 ? 64u : (uint32_t)x.param;
+            break;
+        case RIROS_OP_NOT:
+            o.a = img.u2i[x.in[0]];
+            break;
+        case RIROS_OP_CONCAT:
+            o.a = img.u2i[x.in[0]];
+            o.b = img.u2i[x.in[1]];
+            o.c = nd[x.in[1]].width;
+            break;
+        case RIROS_OP_MUX:
+            o.a = img.u2i[x.in[0]];
+            o.b = img.u2i[x.in[1]];
+            o.c = img.u2i[x.in[2]];
+            break;
+        default:
+            o.a = img.u2i[x.in[0]];
+            o.b = img.u2i[x.in[1]];
+            break;
+        }
+    }
+
+    // Fan-out tables in internal numbering; a user that reads a node twice is listed once.
+    std::vector<std::vector<uint32_t>> fo(N), rfo(N);
+    for (uint32_t i = 0; i < N; ++i) {
+        const Desc& o = img.desc[i];
+        if (o.op == RIROS_OP_REG) {
+            rfo[o.a].push_back(i);
+            continue;
+        }
+        if (!op_is_comb(o.op)) continue;
+        int ar = op_arity(o.op);
+        uint32_t ins[3] = {o.a, o.b, o.c};
+        for (int k = 0; k < ar; ++k) {
+            bool dup = false;
+            for (int j = 0; j < k; ++j) dup |= ins[j] == ins[k];
+            if (!dup) fo[ins[k]].push_back(i);
+        }
+    }
+    img.fo_off.assign(N + 1, 0);
+    img.rfo_off.assign(N + 1, 0);
+    for (uint32_t i = 0; i < N; ++i) {
+        img.fo_off[i + 1] = img.fo_off[i] + (uint32_t)fo[i].size();
+        img.rfo_off[i + 1] = img.rfo_off[i] + (uint32_t)rfo[i].size();
+    }
+    img.fo.clear();
+    img.fo_lvl.clear();
+    img.rfo.clear();
+    for (uint32_t i = 0; i < N; ++i) {
+        std::sort(fo[i].begin(), fo[i].end());
+        for (uint32_t u : fo[i]) { img.fo.push_back(u); img.fo_lvl.push_back(img.level[u]); }
+        for (uint32_t r : rfo[i]) img.rfo.push_back(r);
+        if (!fo[i].empty()) img.desc[i].flags |= DF_COMBFO;
+        if (!rfo[i].empty()) img.desc[i].flags |= DF_REGFO;
+    }
+    std::vector<uint8_t> seen(N, 0);
+    img.po.clear();
+    for (uint32_t i = 0; i < d.num_po; ++i) {
+        uint32_t p = img.u2i[d.po[i]];
+        if (!seen[p]) { seen[p] = 1; img.po.push_back(p); img.desc[p].flags |= DF_PO; }
+    }
+    return RIROS_OK;
+}
+
+}  // namespace riros

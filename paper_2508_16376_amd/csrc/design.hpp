@@ -1,0 +1,45 @@
+// Host-side design compiler: validation, levelisation, level-major
+// renumbering and the fan-out tables the kernels walk.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "riros.h"
+
+namespace riros {
+
+// 16-byte node descriptor in internal (level-major) numbering.
+//   comb ops    a, b, c = operand ids (per arity); SHL/SHR/SLICE: b = shift
+//               (clamped to 64); CONCAT: c = width of operand b
+//   PI          a = stimulus column
+//   CONST       a, b = value (low, high word)
+//   REG         a = D node; b, c = reset value (low, high word)
+struct Desc {
+    uint8_t op, width, flags, pad;
+    uint32_t a, b, c;
+};
+static_assert(sizeof(Desc) == 16, "descriptor layout");
+
+enum : uint8_t { DF_PO = 1, DF_REGFO = 2, DF_COMBFO = 4 };
+
+struct Image {
+    uint32_t N = 0, L = 0, R = 0, npi = 0;
+    std::vector<uint32_t> u2i, i2u;         // user id <-> internal id
+    std::vector<uint32_t> lvl_off;          // L+1 node offsets per level
+    std::vector<uint32_t> level;            // per internal node
+    std::vector<Desc> desc;
+    std::vector<uint32_t> fo_off, fo, fo_lvl;   // combinational users (deduplicated)
+    std::vector<uint32_t> rfo_off, rfo;         // registers whose D is this node
+    std::vector<uint32_t> po;                   // internal ids, deduplicated
+};
+
+// Registers take internal ids 0..R-1, then the other level-0 nodes (PI,
+// CONST), then levels 1..L-1.  Returns RIROS_OK or an error code with `err`.
+int build_image(const riros_design_desc& desc, Image& img, std::string& err);
+
+int op_arity(uint8_t op);
+bool op_is_comb(uint8_t op);
+
+}  // namespace riros

@@ -1,0 +1,86 @@
+// Device helpers shared by the kernels: operator evaluation, forcing, wave scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "design.hpp"
+
+namespace riros {
+
+__device__ __forceinline__ uint64_t width_mask(uint32_t w)
+{
+    return w >= 64 ? ~0ull : ((1ull << w) - 1ull);
+}
+
+__device__ __forceinline__ int dev_arity(uint32_t op)
+{
+    // CONST PI REG ADD SUB AND OR XOR NOT MUX SHL SHR EQ NE ULT SLICE CONCAT MUL
+    // 0     0  1   2   2   2   2  2   1   3   1   1   2  2  2   1     2      2
+    return op == RIROS_OP_MUX ? 3
+         : (op == RIROS_OP_NOT || op == RIROS_OP_SHL || op == RIROS_OP_SHR || op == RIROS_OP_SLICE) ? 1
+         : 2;
+}
+
+// Result of a combinational operator on masked operand values (the operator
+// table of riros.h).  Shift amounts and the CONCAT low width live in the
+// descriptor (b and c fields).
+__device__ __forceinline__ uint64_t apply_op(const Desc& d, uint64_t x0, uint64_t x1, uint64_t x2)
+{
+    uint64_t r;
+    switch (d.op) {
+    case RIROS_OP_ADD: r = x0 + x1; break;
+    case RIROS_OP_SUB: r = x0 - x1; break;
+    case RIROS_OP_AND: r = x0 & x1; break;
+    case RIROS_OP_OR: r = x0 | x1; break;
+    case RIROS_OP_XOR: r = x0 ^ x1; break;
+    case RIROS_OP_NOT: r = ~x0; break;
+    case RIROS_OP_MUX: r = x0 != 0 ? x2 : x1; break;
+    case RIROS_OP_SHL: r = d.b >= 64 ? 0 : (x0 << d.b); break;
+    case RIROS_OP_SHR:
+    case RIROS_OP_SLICE: r = d.b >= 64 ? 0 : (x0 >> d.b); break;
+    case RIROS_OP_EQ: r = x0 == x1; break;
+    case RIROS_OP_NE: r = x0 != x1; break;
+    case RIROS_OP_ULT: r = x0 < x1; break;
+    case RIROS_OP_CONCAT: r = (d.c >= 64 ? 0 : (x0 << d.c)) | x1; break;
+    case RIROS_OP_MUL: r = x0 * x1; break;
+    default: r = 0; break;
+    }
+    return r & width_mask(d.width);
+}
+
+// Stuck-at forcing of one bit (Sec. IV-A: the faulty value replaces the
+// computed one at the injected node).
+__device__ __forceinline__ uint64_t force_bit(uint64_t v, uint32_t bit, uint32_t stuck)
+{
+    const uint64_t m = 1ull << bit;
+    return stuck ? (v | m) : (v & ~m);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t make_u64(uint32_t lo, uint32_t hi)
+{
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+}  // namespace riros

@@ -1,0 +1,397 @@
+// C interface of the simulator: design and golden-trace handles, fault
+// simulation entry point, errors and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "design.hpp"
+#include "kernels.hpp"
+#include "riros.h"
+#include "twod.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+thread_local hipEvent_t g_ev0 = nullptr, g_ev1 = nullptr;
+thread_local bool g_ev_valid = false;
+
+int set_err(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_err(hipError_t e, const char* what)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_err = buf;
+    return e == hipErrorOutOfMemory ? RIROS_ENOMEM : RIROS_EDEVICE;
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t _e = (call);                     \
+        if (_e != hipSuccess) return hip_err(_e, what); \
+    } while (0)
+
+template <class T>
+hipError_t dev_upload(T** dst, const std::vector<T>& src)
+{
+    size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return hipSuccess;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct riros_design_s {
+    riros::Image img;
+    int device = 0;
+    int num_cu = 0;
+    riros::DevDesign dev{};
+    std::vector<void*> owned;
+    // plain-kernel workspace (grow-only)
+    riros::Slot* ws_slots = nullptr;
+    size_t ws_slots_cap = 0;
+    uint64_t* ws_regs = nullptr;
+    size_t ws_regs_cap = 0;
+    uint64_t stamp_next = 0;
+    // two-dimensional kernel workspace
+    riros::TwoDWorkspace twod{};
+    // staging for host-side inputs and outputs
+    void* stage = nullptr;
+    size_t stage_cap = 0;
+    riros_coverage* d_cov = nullptr;
+    uint32_t* d_bad = nullptr;
+};
+
+struct riros_golden_s {
+    riros_design d = nullptr;
+    uint32_t T = 0;
+    uint64_t* G = nullptr;
+};
+
+static void free_design_mem(riros_design d)
+{
+    for (void* p : d->owned) (void)hipFree(p);
+    d->owned.clear();
+    if (d->ws_slots) (void)hipFree(d->ws_slots);
+    if (d->ws_regs) (void)hipFree(d->ws_regs);
+    if (d->stage) (void)hipFree(d->stage);
+    if (d->d_cov) (void)hipFree(d->d_cov);
+    if (d->d_bad) (void)hipFree(d->d_bad);
+    riros::twod_free(d->twod);
+}
+
+extern "C" {
+
+const char* riros_last_error(void) { return g_err.c_str(); }
+
+int riros_load_design(const riros_design_desc* desc, riros_design* out)
+{
+    if (!desc || !out) return set_err(RIROS_EINVAL, "NULL argument");
+    riros_design d = new (std::nothrow) riros_design_s();
+    if (!d) return set_err(RIROS_ENOMEM, "host allocation failed");
+    std::string err;
+    int rc = riros::build_image(*desc, d->img, err);
+    if (rc != RIROS_OK) {
+        delete d;
+        return set_err(rc, err);
+    }
+    hipError_t e = hipGetDevice(&d->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device);
+    if (e != hipSuccess) {
+        delete d;
+        return hip_err(e, "device query");
+    }
+    const riros::Image& im = d->img;
+    std::vector<uint8_t> uwidth(im.N);
+    for (uint32_t n = 0; n < im.N; ++n) uwidth[n] = desc->nodes[n].width;
+    riros::Desc* p_desc = nullptr;
+    uint32_t *p_lvl = nullptr, *p_level = nullptr, *p_fo_off = nullptr, *p_fo = nullptr, *p_fo_lvl = nullptr,
+             *p_rfo_off = nullptr, *p_rfo = nullptr, *p_u2i = nullptr;
+    uint8_t* p_uw = nullptr;
+    hipError_t es[10] = {
+        dev_upload(&p_desc, im.desc),     dev_upload(&p_lvl, im.lvl_off), dev_upload(&p_level, im.level),
+        dev_upload(&p_fo_off, im.fo_off), dev_upload(&p_fo, im.fo),       dev_upload(&p_fo_lvl, im.fo_lvl),
+        dev_upload(&p_rfo_off, im.rfo_off), dev_upload(&p_rfo, im.rfo),   dev_upload(&p_u2i, im.u2i),
+        dev_upload(&p_uw, uwidth)};
+    for (void* p : {(void*)p_desc, (void*)p_lvl, (void*)p_level, (void*)p_fo_off, (void*)p_fo, (void*)p_fo_lvl,
+                    (void*)p_rfo_off, (void*)p_rfo, (void*)p_u2i, (void*)p_uw})
+        if (p) d->owned.push_back(p);
+    for (hipError_t x : es)
+        if (x != hipSuccess) {
+            free_design_mem(d);
+            delete d;
+            return hip_err(x, "design upload");
+        }
+    d->dev = riros::DevDesign{p_desc, p_lvl, p_level, p_fo_off, p_fo, p_fo_lvl, p_rfo_off, p_rfo, p_u2i, p_uw,
+                              im.N, im.L, im.R, im.npi};
+    e = hipMalloc((void**)&d->d_cov, sizeof(riros_coverage));
+    if (e == hipSuccess) e = hipMalloc((void**)&d->d_bad, sizeof(uint32_t));
+    if (e != hipSuccess) {
+        free_design_mem(d);
+        delete d;
+        return hip_err(e, "design allocation");
+    }
+    *out = d;
+    return RIROS_OK;
+}
+
+void riros_free_design(riros_design d)
+{
+    if (!d) return;
+    DeviceGuard g(d->device);
+    (void)hipDeviceSynchronize();
+    free_design_mem(d);
+    delete d;
+}
+
+int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels, uint32_t* num_regs)
+{
+    if (!d) return set_err(RIROS_EINVAL, "NULL design");
+    if (num_nodes) *num_nodes = d->img.N;
+    if (num_levels) *num_levels = d->img.L;
+    if (num_regs) *num_regs = d->img.R;
+    return RIROS_OK;
+}
+
+int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream, riros_golden* out)
+{
+    if (!d || !out) return set_err(RIROS_EINVAL, "NULL argument");
+    if (T == 0) return set_err(RIROS_EINVAL, "T must be positive");
+    if (d->img.npi > 0 && !stimulus) return set_err(RIROS_EINVAL, "stimulus is NULL");
+    DeviceGuard guard(d->device);
+    hipStream_t s = (hipStream_t)stream;
+    riros_golden g = new (std::nothrow) riros_golden_s();
+    if (!g) return set_err(RIROS_ENOMEM, "host allocation failed");
+    g->d = d;
+    g->T = T;
+    const size_t gbytes = (size_t)T * d->img.N * sizeof(uint64_t);
+    const size_t sbytes = std::max<size_t>((size_t)T * d->img.npi, 1) * sizeof(uint64_t);
+    uint64_t* stim = nullptr;
+    hipError_t e = hipMalloc((void**)&g->G, gbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&stim, sbytes);
+    if (e == hipSuccess && d->img.npi > 0)
+        e = hipMemcpyAsync(stim, stimulus, (size_t)T * d->img.npi * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = riros::launch_golden(d->dev, stim, T, g->G, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (stim) (void)hipFree(stim);
+    if (e != hipSuccess) {
+        if (g->G) (void)hipFree(g->G);
+        delete g;
+        return hip_err(e, "golden simulation");
+    }
+    *out = g;
+    return RIROS_OK;
+}
+
+void riros_free_golden(riros_golden g)
+{
+    if (!g) return;
+    DeviceGuard guard(g->d->device);
+    (void)hipDeviceSynchronize();
+    if (g->G) (void)hipFree(g->G);
+    delete g;
+}
+
+int riros_golden_read(riros_golden g, uint32_t t0, uint32_t nt, uint64_t* out)
+{
+    if (!g || !out) return set_err(RIROS_EINVAL, "NULL argument");
+    if ((uint64_t)t0 + nt > g->T) return set_err(RIROS_EINVAL, "cycle range outside the trace");
+    DeviceGuard guard(g->d->device);
+    const uint32_t N = g->d->img.N;
+    std::vector<uint64_t> buf((size_t)nt * N);
+    HIP_TRY(hipMemcpy(buf.data(), g->G + (size_t)t0 * N, buf.size() * sizeof(uint64_t), hipMemcpyDeviceToHost),
+            "golden read");
+    const std::vector<uint32_t>& i2u = g->d->img.i2u;
+    for (uint32_t t = 0; t < nt; ++t)
+        for (uint32_t i = 0; i < N; ++i) out[(size_t)t * N + i2u[i]] = buf[(size_t)t * N + i];
+    return RIROS_OK;
+}
+
+int riros_last_kernel_ms(float* ms)
+{
+    if (!ms) return set_err(RIROS_EINVAL, "NULL argument");
+    if (!g_ev_valid) return set_err(RIROS_EINVAL, "no fault simulation recorded on this thread");
+    HIP_TRY(hipEventSynchronize(g_ev1), "event sync");
+    HIP_TRY(hipEventElapsedTime(ms, g_ev0, g_ev1), "event time");
+    return RIROS_OK;
+}
+
+static int ensure_stage(riros_design d, size_t bytes)
+{
+    if (d->stage_cap >= bytes) return RIROS_OK;
+    if (d->stage) (void)hipFree(d->stage);
+    d->stage = nullptr;
+    d->stage_cap = 0;
+    HIP_TRY(hipMalloc(&d->stage, bytes), "staging allocation");
+    d->stage_cap = bytes;
+    return RIROS_OK;
+}
+
+static int ensure_plain_ws(riros_design d, uint32_t blocks, hipStream_t s)
+{
+    const size_t nslots = (size_t)blocks * d->img.N;
+    const size_t nregs = std::max<size_t>((size_t)blocks * 2 * d->img.R, 1);
+    if (d->ws_slots_cap < nslots) {
+        HIP_TRY(hipStreamSynchronize(s), "workspace sync");
+        if (d->ws_slots) (void)hipFree(d->ws_slots);
+        d->ws_slots = nullptr;
+        d->ws_slots_cap = 0;
+        HIP_TRY(hipMalloc((void**)&d->ws_slots, nslots * sizeof(riros::Slot)), "workspace allocation");
+        HIP_TRY(hipMemsetAsync(d->ws_slots, 0, nslots * sizeof(riros::Slot), s), "workspace clear");
+        d->ws_slots_cap = nslots;
+        d->stamp_next = 0;
+    }
+    if (d->ws_regs_cap < nregs) {
+        HIP_TRY(hipStreamSynchronize(s), "workspace sync");
+        if (d->ws_regs) (void)hipFree(d->ws_regs);
+        d->ws_regs = nullptr;
+        d->ws_regs_cap = 0;
+        HIP_TRY(hipMalloc((void**)&d->ws_regs, nregs * sizeof(uint64_t)), "workspace allocation");
+        d->ws_regs_cap = nregs;
+    }
+    return RIROS_OK;
+}
+
+int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
+                    const riros_sim_opts* opts, uint32_t* detect, uint64_t* events, riros_coverage* cov)
+{
+    if (!d || !g || !opts) return set_err(RIROS_EINVAL, "NULL argument");
+    if (g->d != d) return set_err(RIROS_EINVAL, "golden trace belongs to another design");
+    if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
+    if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
+        return set_err(RIROS_EINVAL, "unknown mode");
+    if (opts->waves_per_cu < 0 || opts->light_cap < 0 || opts->chunk < 0)
+        return set_err(RIROS_EINVAL, "negative option");
+    DeviceGuard guard(d->device);
+    hipStream_t s = (hipStream_t)opts->stream;
+    const bool on_dev = opts->io_on_device != 0;
+    const uint32_t T = g->T;
+    const riros::Image& im = d->img;
+
+    if (!g_ev0) {
+        HIP_TRY(hipEventCreate(&g_ev0), "event create");
+        HIP_TRY(hipEventCreate(&g_ev1), "event create");
+    }
+
+    // Faults: validate, and stage host lists on the device.
+    const riros_fault* d_faults = faults;
+    uint32_t* d_detect = detect;
+    uint64_t* d_events = events;
+    const float* d_prio = opts->priority;
+    if (!on_dev) {
+        for (uint32_t i = 0; i < F; ++i) {
+            const riros_fault& f = faults[i];
+            if (f.site >= im.N || f.stuck > 1 || f.bit >= d->img.desc[im.u2i[f.site]].width) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "fault %u: site %u bit %u stuck %u invalid", i, f.site, f.bit,
+                              f.stuck);
+                return set_err(RIROS_EINVAL, buf);
+            }
+        }
+        if (F == 0) {
+            if (cov) *cov = riros_coverage{0, 0, 0, 0};
+            return RIROS_OK;
+        }
+        const size_t fb = (size_t)F * sizeof(riros_fault), db = (size_t)F * 4, eb = (size_t)F * 8,
+                     pb = opts->priority ? (size_t)F * 4 : 0;
+        int rc = ensure_stage(d, fb + db + eb + pb + 256);
+        if (rc) return rc;
+        char* base = (char*)d->stage;
+        d_faults = (const riros_fault*)base;
+        d_detect = (uint32_t*)(base + fb);
+        d_events = (uint64_t*)(base + fb + db + (8 - (fb + db) % 8) % 8);
+        HIP_TRY(hipMemcpyAsync((void*)d_faults, faults, fb, hipMemcpyHostToDevice, s), "fault upload");
+        if (opts->priority) {
+            float* dp = (float*)((char*)d_events + eb);
+            HIP_TRY(hipMemcpyAsync(dp, opts->priority, pb, hipMemcpyHostToDevice, s), "priority upload");
+            d_prio = dp;
+        }
+    } else {
+        if (F == 0) {
+            if (cov) HIP_TRY(hipMemsetAsync(cov, 0, sizeof(riros_coverage), s), "coverage clear");
+            return RIROS_OK;
+        }
+        HIP_TRY(hipMemsetAsync(d->d_bad, 0, sizeof(uint32_t), s), "validate clear");
+        HIP_TRY(riros::launch_validate_faults(d->dev, faults, F, d->d_bad, s), "validate launch");
+        uint32_t bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, d->d_bad, sizeof bad, hipMemcpyDeviceToHost, s), "validate read");
+        HIP_TRY(hipStreamSynchronize(s), "validate sync");
+        if (bad) return set_err(RIROS_EINVAL, std::to_string(bad) + " invalid faults in device fault list");
+    }
+
+    if (opts->mode == RIROS_MODE_PLAIN) {
+        const size_t lds = riros::plain_lds_bytes(d->dev);
+        if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the plain kernel's LDS bitmap");
+        int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 16;
+        const int lds_limit = (int)std::max<size_t>(1, (160 * 1024) / lds);
+        wpc = std::min(std::min(wpc, lds_limit), 32);
+        uint32_t blocks = (uint32_t)std::min<uint64_t>(F, (uint64_t)d->num_cu * wpc);
+        int rc = ensure_plain_ws(d, blocks, s);
+        if (rc) return rc;
+        const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
+        const uint64_t span = per_block * T + 1;
+        if (d->stamp_next + span >= 0xFFFFFFF0ull) {
+            HIP_TRY(hipMemsetAsync(d->ws_slots, 0, d->ws_slots_cap * sizeof(riros::Slot), s), "workspace clear");
+            d->stamp_next = 0;
+        }
+        if (span >= 0xFFFFFFF0ull) return set_err(RIROS_EINVAL, "faults per block times T exceeds 2^32");
+        riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, (uint32_t)d->stamp_next};
+        d->stamp_next += span;
+        HIP_TRY(hipEventRecord(g_ev0, s), "event record");
+        HIP_TRY(riros::launch_fault_plain(d->dev, g->G, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
+                                          d_events, s),
+                "plain fault kernel");
+        HIP_TRY(hipEventRecord(g_ev1, s), "event record");
+    } else {
+        riros::TwoDParams p;
+        p.theta = opts->theta;
+        p.light_cap = opts->light_cap;
+        p.chunk = opts->chunk;
+        p.waves_per_cu = opts->waves_per_cu;
+        p.num_cu = d->num_cu;
+        std::string err;
+        int rc = riros::run_twod(d->dev, d->twod, g->G, T, d_faults, d_prio, F, opts->drop ? 1 : 0, p, d_detect,
+                                 d_events, g_ev0, g_ev1, s, err);
+        if (rc) return set_err(rc, err);
+    }
+    g_ev_valid = true;
+
+    riros_coverage* cov_dst = on_dev ? cov : d->d_cov;
+    if (cov) HIP_TRY(riros::launch_coverage(d_detect, d_events, F, T, cov_dst, s), "coverage");
+    if (!on_dev) {
+        HIP_TRY(hipMemcpyAsync(detect, d_detect, (size_t)F * 4, hipMemcpyDeviceToHost, s), "detect download");
+        if (events)
+            HIP_TRY(hipMemcpyAsync(events, d_events, (size_t)F * 8, hipMemcpyDeviceToHost, s), "events download");
+        if (cov) HIP_TRY(hipMemcpyAsync(cov, d->d_cov, sizeof(riros_coverage), hipMemcpyDeviceToHost, s),
+                         "coverage download");
+        HIP_TRY(hipStreamSynchronize(s), "fault simulation sync");
+    }
+    return RIROS_OK;
+}
+
+}  // extern "C"

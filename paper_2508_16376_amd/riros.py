@@ -1,0 +1,230 @@
+"""Python binding of the C interface in include/riros.h (argument marshalling only).
+
+Every simulation step runs in the HIP library ``_build/libriros.so``; this
+module only converts arguments.  Importing it raises if the library has not
+been built (``python -m paper_2508_16376_amd.build``); there is no fallback.
+Device buffers and streams may be passed as torch tensors / streams, whose
+pointers are handed to the library unchanged.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libriros.so")
+
+RIROS_OK = 0
+RIROS_EINVAL = -1
+RIROS_ECYCLE = -2
+RIROS_ENOMEM = -3
+RIROS_EDEVICE = -4
+UNDETECTED = 0xFFFFFFFF
+MODE_PLAIN = 0
+MODE_TWO_D = 1
+
+EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros_free_golden",
+            "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
+            "riros_last_error"]
+
+
+class RirosError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"riros error {code}: {msg}")
+        self.code = code
+
+
+class _DesignDesc(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_uint32), ("nodes", ctypes.c_void_p),
+                ("num_pi", ctypes.c_uint32), ("num_po", ctypes.c_uint32), ("po", ctypes.c_void_p)]
+
+
+class SimOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("drop", ctypes.c_int32), ("io_on_device", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("priority", ctypes.c_void_p), ("theta", ctypes.c_float),
+                ("light_cap", ctypes.c_int32), ("chunk", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class Coverage(ctypes.Structure):
+    _fields_ = [("detected", ctypes.c_uint64), ("total", ctypes.c_uint64),
+                ("fault_cycles", ctypes.c_uint64), ("events", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def _hip_runtimes_mapped() -> set[str]:
+    try:
+        with open("/proc/self/maps") as f:
+            return {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return set()
+
+
+def lib():
+    """The loaded library; raises when it is missing (no CPU fallback exists).
+
+    torch is imported first so that its HIP runtime is the one the library
+    binds to (both carry the soname libamdhip64.so.7); the library's kernels
+    then share streams and device memory with torch tensors.
+    """
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_2508_16376_amd.build)")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes_mapped()
+        if len(runtimes) > 1:
+            raise RuntimeError(f"two HIP runtimes are loaded in this process: {sorted(runtimes)}")
+        P, U, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+        L.riros_load_design.argtypes = [ctypes.POINTER(_DesignDesc), ctypes.POINTER(P)]
+        L.riros_load_design.restype = I
+        L.riros_free_design.argtypes = [P]
+        L.riros_free_design.restype = None
+        L.riros_golden_sim.argtypes = [P, P, U, P, ctypes.POINTER(P)]
+        L.riros_golden_sim.restype = I
+        L.riros_free_golden.argtypes = [P]
+        L.riros_free_golden.restype = None
+        L.riros_golden_read.argtypes = [P, U, U, P]
+        L.riros_golden_read.restype = I
+        L.riros_fault_sim.argtypes = [P, P, P, U, ctypes.POINTER(SimOpts), P, P, ctypes.POINTER(Coverage)]
+        L.riros_fault_sim.restype = I
+        L.riros_design_info.argtypes = [P, ctypes.POINTER(U), ctypes.POINTER(U), ctypes.POINTER(U)]
+        L.riros_design_info.restype = I
+        L.riros_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
+        L.riros_last_kernel_ms.restype = I
+        L.riros_last_error.argtypes = []
+        L.riros_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != RIROS_OK:
+        raise RirosError(rc, lib().riros_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Design:
+    """riros_load_design handle."""
+
+    def __init__(self, design):
+        self._nodes = np.ascontiguousarray(design.nodes)
+        self._po = np.ascontiguousarray(design.po, dtype=np.uint32)
+        desc = _DesignDesc(self._nodes.size, _ptr(self._nodes), design.num_pi, self._po.size, _ptr(self._po))
+        h = ctypes.c_void_p()
+        _check(lib().riros_load_design(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.num_pi = design.num_pi
+
+    def info(self):
+        n, l, r = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().riros_design_info(self.handle, ctypes.byref(n), ctypes.byref(l), ctypes.byref(r)))
+        return {"nodes": n.value, "levels": l.value, "regs": r.value}
+
+    def close(self):
+        if self.handle:
+            lib().riros_free_design(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Golden:
+    """riros_golden_sim handle (trace resident on the device)."""
+
+    def __init__(self, design: Design, stimulus: np.ndarray, T: int, stream=None):
+        stim = np.ascontiguousarray(stimulus[:T], dtype=np.uint64)
+        if stim.shape[0] < T:
+            raise ValueError("stimulus has fewer rows than T")
+        h = ctypes.c_void_p()
+        _check(lib().riros_golden_sim(design.handle, _ptr(stim), T, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.design = design
+        self.T = T
+
+    def read(self, t0: int = 0, nt: int | None = None) -> np.ndarray:
+        nt = self.T - t0 if nt is None else nt
+        N = self.design.info()["nodes"]
+        out = np.empty((nt, N), dtype=np.uint64)
+        _check(lib().riros_golden_read(self.handle, t0, nt, _ptr(out)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().riros_free_golden(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(mode=MODE_PLAIN, drop=True, io_on_device=False, waves_per_cu=0, priority=None,
+              theta=math.inf, light_cap=0, chunk=0, stream=None) -> SimOpts:
+    return SimOpts(mode, 1 if drop else 0, 1 if io_on_device else 0, waves_per_cu, _ptr(priority),
+                   theta, light_cap, chunk, _stream_ptr(stream))
+
+
+def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_PLAIN, drop=True,
+              waves_per_cu=0, priority=None, theta=math.inf, light_cap=0, chunk=0, stream=None,
+              with_events=True):
+    """riros_fault_sim on host arrays: returns (detect, events, coverage dict)."""
+    fl = np.ascontiguousarray(faults)
+    F = fl.size
+    detect = np.empty(F, dtype=np.uint32)
+    events = np.empty(F, dtype=np.uint64) if with_events else None
+    pr = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
+    opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, chunk, stream)
+    cov = Coverage()
+    _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(fl), F, ctypes.byref(opts), _ptr(detect),
+                                 _ptr(events), ctypes.byref(cov)))
+    return detect, events, cov.as_dict()
+
+
+def fault_sim_device(design: Design, golden: Golden, faults_dev, F: int, detect_dev, events_dev, cov_dev,
+                     opts: SimOpts):
+    """riros_fault_sim with device-resident buffers (asynchronous on opts.stream)."""
+    opts.io_on_device = 1
+    _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(faults_dev), F, ctypes.byref(opts),
+                                 _ptr(detect_dev), _ptr(events_dev),
+                                 ctypes.cast(_ptr(cov_dev), ctypes.POINTER(Coverage)) if cov_dev is not None
+                                 else None))
+
+
+def last_kernel_ms() -> float:
+    ms = ctypes.c_float()
+    _check(lib().riros_last_kernel_ms(ctypes.byref(ms)))
+    return float(ms.value)

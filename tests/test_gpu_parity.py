@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact.
+
+Golden traces, detect cycles and event counts must be identical to the
+oracle's on the same seeded inputs.  Runs on an MI355X only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import Builder, all_faults, faults
+from paper_2508_16376_amd import riros
+from paper_2508_16376_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+UND = riros.UNDETECTED
+MODES = [riros.MODE_PLAIN]
+
+
+def _run(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, **kw):
+    d = riros.Design(design_np)
+    g = riros.Golden(d, stim, T)
+    det, ev, cov = riros.fault_sim(d, g, fl, mode=mode, drop=drop, **kw)
+    return det, ev, cov, d, g
+
+
+def _check(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, variant=1, **kw):
+    print(f"[parity] design={design_np.name} N={design_np.num_nodes} T={T} F={fl.size} mode={mode} "
+          f"drop={drop}", flush=True)
+    det, ev, cov, d, g = _run(design_np, stim, T, fl, mode, drop, **kw)
+    odet, oev = oracle.fault_sim(design_np, stim, T, fl, drop=drop, variant=variant)
+    np.testing.assert_array_equal(det, odet)
+    np.testing.assert_array_equal(ev, oev)
+    assert cov["total"] == fl.size
+    assert cov["detected"] == int((odet != UND).sum())
+    assert cov["fault_cycles"] == oracle.fault_cycles(odet, T)
+    assert cov["events"] == int(oev.sum())
+    return det, ev
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return W.tiny()
+
+
+@pytest.fixture(scope="module")
+def small():
+    return W.medium(seed=777, F=4000, T=300, n_nodes=3000)
+
+
+def test_golden_matches_oracle(tiny, small):
+    for w in (tiny, small):
+        d = riros.Design(w.design)
+        g = riros.Golden(d, w.stimulus, w.T)
+        np.testing.assert_array_equal(g.read(), oracle.golden(w.design, w.stimulus, w.T))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("drop", [True, False])
+def test_tiny_full(tiny, mode, drop):
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, mode, drop, variant=0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("drop", [True, False])
+def test_small_layered_full(small, mode, drop):
+    _check(small.design, small.stimulus, small.T, small.faults, mode, drop)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_medium_full_size(mode):
+    """The medium workload at its full size; every fault compared with the oracle."""
+    w = W.medium()
+    _check(w.design, w.stimulus, w.T, w.faults, mode, True)
+
+
+def _edge_design():
+    b = Builder()
+    a = b.pi(64)
+    c = b.pi(1)
+    k = b.const(64, 0xDEADBEEF12345678)
+    r64 = b.reg(64, init=0x8000000000000001)
+    r1 = b.reg(1, init=1)
+    s = b.node(W.ADD, 64, (a, r64))
+    x = b.node(W.XOR, 64, (s, k))
+    sh = b.node(W.SHL, 64, (x,), 63)
+    sr = b.node(W.SHR, 64, (x,), 64)
+    m = b.node(W.MUX, 64, (r1, x, sh))
+    cc = b.node(W.CONCAT, 64, (b.node(W.SLICE, 32, (m,), 16), b.node(W.SLICE, 32, (a,), 32)))
+    lt = b.node(W.ULT, 1, (cc, x))
+    nt = b.node(W.NOT, 1, (lt,))
+    ml = b.node(W.MUL, 64, (cc, a))
+    b.set_d(r64, ml)
+    b.set_d(r1, b.node(W.XOR, 1, (nt, c)))
+    eq = b.node(W.EQ, 1, (sr, b.const(64, 0)))
+    return b.design([nt, cc, eq, r1], "edge64")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_design_all_faults_all_sites(mode):
+    d = _edge_design()
+    T = 150
+    stim = W.counter_values(99, 0, 2 * T).reshape(T, 2)
+    stim[:, 1] &= np.uint64(1)
+    fl = all_faults(d)                     # includes PI, CONST, REG and output nodes
+    for drop in (True, False):
+        _check(d, stim, T, fl, mode, drop, variant=0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_single_cycle_single_fault_and_duplicates(tiny, mode):
+    w = tiny
+    _check(w.design, w.stimulus, 1, w.faults[:1], mode)
+    dup = np.concatenate([w.faults[:50], w.faults[:50]])
+    det, ev = _check(w.design, w.stimulus, w.T, dup, mode)
+    np.testing.assert_array_equal(det[:50], det[50:])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_no_registers_and_register_chain(mode):
+    b = Builder()
+    p = [b.pi(8) for _ in range(3)]
+    o = b.node(W.SUB, 8, (b.node(W.AND, 8, (p[0], p[1])), p[2]))
+    d = b.design([o], "comb-only")
+    T = 64
+    stim = W.counter_values(3, 0, 3 * T).reshape(T, 3) & np.uint64(255)
+    _check(d, stim, T, all_faults(d), mode, variant=0)
+    b = Builder()
+    x = b.pi(4)
+    regs = [b.reg(4) for _ in range(6)]
+    b.set_d(regs[0], x)
+    for j in range(1, 6):
+        b.set_d(regs[j], regs[j - 1])
+    d = b.design([regs[-1]], "delay-line")
+    stim = (W.counter_values(4, 0, T) & np.uint64(15))[:, None]
+    _check(d, stim, T, all_faults(d), mode, variant=0)
+
+
+def test_faults_in_any_order_give_the_same_results(small):
+    w = small
+    perm = np.argsort(W.counter_values(5, 0, w.faults.size))
+    det, ev, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults)
+    det2, ev2, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults[perm])
+    np.testing.assert_array_equal(det[perm], det2)
+    np.testing.assert_array_equal(ev[perm], ev2)
+
+
+def test_repeated_calls_reuse_workspace(small):
+    """Stamps carry over between calls on one design handle; results must not."""
+    w = small
+    d = riros.Design(w.design)
+    g = riros.Golden(d, w.stimulus, w.T)
+    first = riros.fault_sim(d, g, w.faults)
+    for wpc in (1, 4, 16):
+        again = riros.fault_sim(d, g, w.faults, waves_per_cu=wpc)
+        np.testing.assert_array_equal(first[0], again[0])
+        np.testing.assert_array_equal(first[1], again[1])
+
+
+def test_invalid_fault_rejected(tiny):
+    d = riros.Design(tiny.design)
+    g = riros.Golden(d, tiny.stimulus, tiny.T)
+    bad = tiny.faults[:4].copy()
+    bad["bit"][2] = 70
+    with pytest.raises(riros.RirosError) as e:
+        riros.fault_sim(d, g, bad)
+    assert e.value.code == riros.RIROS_EINVAL
+    bad = tiny.faults[:4].copy()
+    bad["site"][1] = tiny.design.num_nodes
+    with pytest.raises(riros.RirosError):
+        riros.fault_sim(d, g, bad)
+
+
+def test_empty_fault_list(tiny):
+    d = riros.Design(tiny.design)
+    g = riros.Golden(d, tiny.stimulus, tiny.T)
+    det, ev, cov = riros.fault_sim(d, g, tiny.faults[:0])
+    assert det.size == 0 and cov["total"] == 0
+
+
+def test_device_io_matches_host_io(small):
+    import torch
+    w = small
+    d = riros.Design(w.design)
+    g = riros.Golden(d, w.stimulus, w.T)
+    det, ev, cov = riros.fault_sim(d, g, w.faults)
+    dev = torch.device("cuda:0")
+    f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
+    det_dev = torch.empty(w.faults.size, dtype=torch.int32, device=dev)
+    ev_dev = torch.empty(w.faults.size, dtype=torch.int64, device=dev)
+    cov_dev = torch.zeros(4, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    opts = riros.make_opts(riros.MODE_PLAIN, True, True, stream=stream)
+    riros.fault_sim_device(d, g, f_dev, w.faults.size, det_dev, ev_dev, cov_dev, opts)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(det_dev.cpu().numpy().view(np.uint32), det)
+    np.testing.assert_array_equal(ev_dev.cpu().numpy().view(np.uint64), ev)
+    c = cov_dev.cpu().numpy()
+    assert list(c) == [cov["detected"], cov["total"], cov["fault_cycles"], cov["events"]]
