@@ -103,7 +103,9 @@ void riros_free_design(riros_design d);
  * resident in device memory (the "good gate" values every bad gate is compared
  * against, Sec. II-B).  `stimulus` is a host array uint64[T][num_pi], row t =
  * primary-input values of cycle t (masked to each PI's width on use).  The
- * trace takes 8*T*num_nodes bytes of device memory.  Errors: RIROS_EINVAL
+ * trace is kept in three layouts (cycle-major, node-major and one bit-plane
+ * per node bit), about 16*T*num_nodes + T*sum(widths)/8 bytes of device
+ * memory.  Errors: RIROS_EINVAL
  * (T == 0, NULL pointers), RIROS_ENOMEM, RIROS_EDEVICE.  *out is a new handle. */
 int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream,
                      riros_golden* out);
@@ -131,7 +133,10 @@ typedef struct {
                               structural (heavy) path; +inf = all light */
     int32_t light_cap;     /* TWO_D: per-lane divergent-node capacity (0 = default);
                               a lane that overflows is moved to the heavy path */
-    int32_t chunk;         /* TWO_D: faults taken per queue pop (0 = default) */
+    int32_t chunk;         /* reserved, must be 0 */
+    float monitor_rate;    /* TWO_D: a light fault averaging more than this many
+                              events per cycle after its first 8 cycles moves to
+                              the structural path (0 = never) */
     void* stream;
 } riros_sim_opts;
 

@@ -182,20 +182,45 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
     }
     img.fo.clear();
     img.fo_lvl.clear();
+    img.fo_pk.clear();
     img.rfo.clear();
     for (uint32_t i = 0; i < N; ++i) {
         std::sort(fo[i].begin(), fo[i].end());
-        for (uint32_t u : fo[i]) { img.fo.push_back(u); img.fo_lvl.push_back(img.level[u]); }
+        for (uint32_t u : fo[i]) {
+            img.fo.push_back(u);
+            img.fo_lvl.push_back(img.level[u]);
+            img.fo_pk.push_back((uint64_t)u | ((uint64_t)img.level[u] << 32));
+        }
         for (uint32_t r : rfo[i]) img.rfo.push_back(r);
         if (!fo[i].empty()) img.desc[i].flags |= DF_COMBFO;
         if (!rfo[i].empty()) img.desc[i].flags |= DF_REGFO;
     }
     std::vector<uint8_t> seen(N, 0);
     img.po.clear();
+    img.rec.assign(N, NodeRec{});
+    img.bp_off.assign(N, 0);
+    uint32_t rows = 0;
     for (uint32_t i = 0; i < d.num_po; ++i) {
         uint32_t p = img.u2i[d.po[i]];
         if (!seen[p]) { seen[p] = 1; img.po.push_back(p); img.desc[p].flags |= DF_PO; }
     }
+    for (uint32_t i = 0; i < N; ++i) {
+        const Desc& o = img.desc[i];
+        NodeRec& r = img.rec[i];
+        r.op = o.op;
+        r.width = o.width;
+        r.flags = o.flags;
+        r.a = o.a;
+        r.b = o.b;
+        r.c = o.c;
+        r.fo0 = img.fo_off[i];
+        r.fo1 = img.fo_off[i + 1];
+        r.rfo0 = img.rfo_off[i];
+        r.rfo1 = img.rfo_off[i + 1];
+        img.bp_off[i] = rows;
+        rows += o.width;
+    }
+    img.bp_rows = rows;
     return RIROS_OK;
 }
 

@@ -24,6 +24,17 @@ static_assert(sizeof(Desc) == 16, "descriptor layout");
 
 enum : uint8_t { DF_PO = 1, DF_REGFO = 2, DF_COMBFO = 4 };
 
+// 32-byte node record for per-lane walks: the descriptor plus the node's
+// fan-out ranges, so one load gives everything needed to evaluate a node and
+// schedule its users.
+struct NodeRec {
+    uint8_t op, width, flags, pad;
+    uint32_t a, b, c;
+    uint32_t fo0, fo1;     // combinational users: fo[fo0..fo1)
+    uint32_t rfo0, rfo1;   // registers fed: rfo[rfo0..rfo1)
+};
+static_assert(sizeof(NodeRec) == 32, "record layout");
+
 struct Image {
     uint32_t N = 0, L = 0, R = 0, npi = 0;
     std::vector<uint32_t> u2i, i2u;         // user id <-> internal id
@@ -31,8 +42,12 @@ struct Image {
     std::vector<uint32_t> level;            // per internal node
     std::vector<Desc> desc;
     std::vector<uint32_t> fo_off, fo, fo_lvl;   // combinational users (deduplicated)
+    std::vector<uint64_t> fo_pk;                // user id | level << 32
     std::vector<uint32_t> rfo_off, rfo;         // registers whose D is this node
     std::vector<uint32_t> po;                   // internal ids, deduplicated
+    std::vector<NodeRec> rec;                   // per internal node
+    std::vector<uint32_t> bp_off;               // first bit-plane row of each node (prefix sum of widths)
+    uint32_t bp_rows = 0;                       // total bit-plane rows (sum of widths)
 };
 
 // Registers take internal ids 0..R-1, then the other level-0 nodes (PI,

@@ -24,11 +24,12 @@ __device__ __forceinline__ int dev_arity(uint32_t op)
 
 // Result of a combinational operator on masked operand values (the operator
 // table of riros.h).  Shift amounts and the CONCAT low width live in the
-// descriptor (b and c fields).
-__device__ __forceinline__ uint64_t apply_op(const Desc& d, uint64_t x0, uint64_t x1, uint64_t x2)
+// descriptor's b and c fields (pb, pc).
+__device__ __forceinline__ uint64_t apply_opw(uint32_t op, uint32_t width, uint32_t pb, uint32_t pc, uint64_t x0,
+                                              uint64_t x1, uint64_t x2)
 {
     uint64_t r;
-    switch (d.op) {
+    switch (op) {
     case RIROS_OP_ADD: r = x0 + x1; break;
     case RIROS_OP_SUB: r = x0 - x1; break;
     case RIROS_OP_AND: r = x0 & x1; break;
@@ -36,17 +37,22 @@ __device__ __forceinline__ uint64_t apply_op(const Desc& d, uint64_t x0, uint64_
     case RIROS_OP_XOR: r = x0 ^ x1; break;
     case RIROS_OP_NOT: r = ~x0; break;
     case RIROS_OP_MUX: r = x0 != 0 ? x2 : x1; break;
-    case RIROS_OP_SHL: r = d.b >= 64 ? 0 : (x0 << d.b); break;
+    case RIROS_OP_SHL: r = pb >= 64 ? 0 : (x0 << pb); break;
     case RIROS_OP_SHR:
-    case RIROS_OP_SLICE: r = d.b >= 64 ? 0 : (x0 >> d.b); break;
+    case RIROS_OP_SLICE: r = pb >= 64 ? 0 : (x0 >> pb); break;
     case RIROS_OP_EQ: r = x0 == x1; break;
     case RIROS_OP_NE: r = x0 != x1; break;
     case RIROS_OP_ULT: r = x0 < x1; break;
-    case RIROS_OP_CONCAT: r = (d.c >= 64 ? 0 : (x0 << d.c)) | x1; break;
+    case RIROS_OP_CONCAT: r = (pc >= 64 ? 0 : (x0 << pc)) | x1; break;
     case RIROS_OP_MUL: r = x0 * x1; break;
     default: r = 0; break;
     }
-    return r & width_mask(d.width);
+    return r & width_mask(width);
+}
+
+__device__ __forceinline__ uint64_t apply_op(const Desc& d, uint64_t x0, uint64_t x1, uint64_t x2)
+{
+    return apply_opw(d.op, d.width, d.b, d.c, x0, x1, x2);
 }
 
 // Stuck-at forcing of one bit (Sec. IV-A: the faulty value replaces the

@@ -20,14 +20,32 @@ struct DevDesign {
     const uint32_t* rfo;
     const uint32_t* u2i;
     const uint8_t* uwidth;     // width per user node id
+    const NodeRec* rec;        // per internal node: descriptor + fan-out ranges
+    const uint64_t* fo_pk;     // fan-out entries: user id | user level << 32
+    const uint32_t* bp_off;    // per internal node: first bit-plane row
     uint32_t N, L, R, npi;
+    uint32_t bp_rows;
 };
+
+// Golden trace in three layouts: row-major G[t][n] (per-cycle sweeps of the
+// structural path), node-major Gn[n][t] (a lane following one node over
+// consecutive cycles hits the same cache line), and bit-planes
+// Bp[row][w] with row = bp_off[n] + bit, word w holding cycles 64w..64w+63.
+struct GoldenView {
+    const uint64_t* G;
+    const uint64_t* Gn;
+    const uint64_t* Bp;
+    uint32_t T;
+    uint32_t TW;   // words per bit-plane row = ceil(T / 64)
+};
+
+hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t T, uint64_t* Gn, uint64_t* Bp,
+                                 hipStream_t s);
 
 // Per-node faulty value with the cycle stamp that makes it valid.
 struct __attribute__((aligned(16))) Slot {
     uint64_t v;
-    uint32_t stamp;
-    uint32_t pad;
+    uint64_t stamp;
 };
 
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s);
@@ -35,7 +53,7 @@ hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, u
 struct PlainWorkspace {
     Slot* slots;          // [blocks][N]
     uint64_t* regs;       // [blocks][2][R]
-    uint32_t stamp_base;
+    uint64_t stamp_base;  // stamps above this value are unused in every block's slots
 };
 
 // Bytes of dynamic LDS the plain kernel needs for a design.

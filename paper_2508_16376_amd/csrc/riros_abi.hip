@@ -90,8 +90,19 @@ struct riros_design_s {
 struct riros_golden_s {
     riros_design d = nullptr;
     uint32_t T = 0;
-    uint64_t* G = nullptr;
+    uint64_t* G = nullptr;    // row-major [T][N]
+    uint64_t* Gn = nullptr;   // node-major [N][T]
+    uint64_t* Bp = nullptr;   // bit-planes [bp_rows][ceil(T/64)]
+    riros::GoldenView view() const { return riros::GoldenView{G, Gn, Bp, T, (T + 63) / 64}; }
 };
+
+static void free_golden_mem(riros_golden g)
+{
+    if (g->G) (void)hipFree(g->G);
+    if (g->Gn) (void)hipFree(g->Gn);
+    if (g->Bp) (void)hipFree(g->Bp);
+    g->G = g->Gn = g->Bp = nullptr;
+}
 
 static void free_design_mem(riros_design d)
 {
@@ -133,12 +144,15 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
     uint32_t *p_lvl = nullptr, *p_level = nullptr, *p_fo_off = nullptr, *p_fo = nullptr, *p_fo_lvl = nullptr,
              *p_rfo_off = nullptr, *p_rfo = nullptr, *p_u2i = nullptr;
     uint8_t* p_uw = nullptr;
-    hipError_t es[10] = {
+    riros::NodeRec* p_rec = nullptr;
+    uint32_t* p_bp = nullptr;
+    uint64_t* p_fopk = nullptr;
+    hipError_t es[13] = {dev_upload(&p_rec, im.rec), dev_upload(&p_bp, im.bp_off), dev_upload(&p_fopk, im.fo_pk),
         dev_upload(&p_desc, im.desc),     dev_upload(&p_lvl, im.lvl_off), dev_upload(&p_level, im.level),
         dev_upload(&p_fo_off, im.fo_off), dev_upload(&p_fo, im.fo),       dev_upload(&p_fo_lvl, im.fo_lvl),
         dev_upload(&p_rfo_off, im.rfo_off), dev_upload(&p_rfo, im.rfo),   dev_upload(&p_u2i, im.u2i),
         dev_upload(&p_uw, uwidth)};
-    for (void* p : {(void*)p_desc, (void*)p_lvl, (void*)p_level, (void*)p_fo_off, (void*)p_fo, (void*)p_fo_lvl,
+    for (void* p : {(void*)p_rec, (void*)p_bp, (void*)p_fopk, (void*)p_desc, (void*)p_lvl, (void*)p_level, (void*)p_fo_off, (void*)p_fo, (void*)p_fo_lvl,
                     (void*)p_rfo_off, (void*)p_rfo, (void*)p_u2i, (void*)p_uw})
         if (p) d->owned.push_back(p);
     for (hipError_t x : es)
@@ -148,7 +162,7 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
             return hip_err(x, "design upload");
         }
     d->dev = riros::DevDesign{p_desc, p_lvl, p_level, p_fo_off, p_fo, p_fo_lvl, p_rfo_off, p_rfo, p_u2i, p_uw,
-                              im.N, im.L, im.R, im.npi};
+                              p_rec, p_fopk, p_bp, im.N, im.L, im.R, im.npi, im.bp_rows};
     e = hipMalloc((void**)&d->d_cov, sizeof(riros_coverage));
     if (e == hipSuccess) e = hipMalloc((void**)&d->d_bad, sizeof(uint32_t));
     if (e != hipSuccess) {
@@ -190,17 +204,21 @@ int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void*
     g->d = d;
     g->T = T;
     const size_t gbytes = (size_t)T * d->img.N * sizeof(uint64_t);
+    const size_t bpbytes = std::max<size_t>((size_t)d->img.bp_rows * ((T + 63) / 64), 1) * sizeof(uint64_t);
     const size_t sbytes = std::max<size_t>((size_t)T * d->img.npi, 1) * sizeof(uint64_t);
     uint64_t* stim = nullptr;
     hipError_t e = hipMalloc((void**)&g->G, gbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->Gn, gbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->Bp, bpbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&stim, sbytes);
     if (e == hipSuccess && d->img.npi > 0)
         e = hipMemcpyAsync(stim, stimulus, (size_t)T * d->img.npi * sizeof(uint64_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = riros::launch_golden(d->dev, stim, T, g->G, s);
+    if (e == hipSuccess) e = riros::launch_golden_layouts(d->dev, g->G, T, g->Gn, g->Bp, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (stim) (void)hipFree(stim);
     if (e != hipSuccess) {
-        if (g->G) (void)hipFree(g->G);
+        free_golden_mem(g);
         delete g;
         return hip_err(e, "golden simulation");
     }
@@ -213,7 +231,7 @@ void riros_free_golden(riros_golden g)
     if (!g) return;
     DeviceGuard guard(g->d->device);
     (void)hipDeviceSynchronize();
-    if (g->G) (void)hipFree(g->G);
+    free_golden_mem(g);
     delete g;
 }
 
@@ -285,8 +303,8 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
     if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
         return set_err(RIROS_EINVAL, "unknown mode");
-    if (opts->waves_per_cu < 0 || opts->light_cap < 0 || opts->chunk < 0)
-        return set_err(RIROS_EINVAL, "negative option");
+    if (opts->waves_per_cu < 0 || opts->light_cap < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f))
+        return set_err(RIROS_EINVAL, "invalid option (negative count, nonzero chunk or bad monitor_rate)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -354,33 +372,44 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         int rc = ensure_plain_ws(d, blocks, s);
         if (rc) return rc;
         const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
-        const uint64_t span = per_block * T + 1;
-        if (d->stamp_next + span >= 0xFFFFFFF0ull) {
-            HIP_TRY(hipMemsetAsync(d->ws_slots, 0, d->ws_slots_cap * sizeof(riros::Slot), s), "workspace clear");
-            d->stamp_next = 0;
-        }
-        if (span >= 0xFFFFFFF0ull) return set_err(RIROS_EINVAL, "faults per block times T exceeds 2^32");
-        riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, (uint32_t)d->stamp_next};
-        d->stamp_next += span;
+        riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_next};
+        d->stamp_next += per_block * T + 1;
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
         HIP_TRY(riros::launch_fault_plain(d->dev, g->G, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
                                           d_events, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
     } else {
+        const size_t lds = riros::plain_lds_bytes(d->dev);
+        if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");
+        const int lds_limit = (int)std::max<size_t>(1, (160 * 1024) / lds);
+        int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 12;
+        wpc = std::min(std::min(wpc, lds_limit), 32);
+        const uint32_t heavy_blocks = (uint32_t)d->num_cu * (uint32_t)wpc;
+        int rc = ensure_plain_ws(d, heavy_blocks, s);
+        if (rc) return rc;
+        riros::PlainWorkspace hws{d->ws_slots, d->ws_regs, d->stamp_next};
+        d->stamp_next += 2 * ((uint64_t)F * T + 1);
         riros::TwoDParams p;
+        p.monitor_rate = opts->monitor_rate;
         p.theta = opts->theta;
         p.light_cap = opts->light_cap;
         p.chunk = opts->chunk;
         p.waves_per_cu = opts->waves_per_cu;
         p.num_cu = d->num_cu;
         std::string err;
-        int rc = riros::run_twod(d->dev, d->twod, g->G, T, d_faults, d_prio, F, opts->drop ? 1 : 0, p, d_detect,
-                                 d_events, g_ev0, g_ev1, s, err);
+        rc = riros::run_twod(d->dev, d->twod, g->view(), d_faults, d_prio, F, opts->drop ? 1 : 0, p, hws,
+                             heavy_blocks, d_detect, d_events, g_ev0, g_ev1, s, err);
         if (rc) return set_err(rc, err);
     }
     g_ev_valid = true;
 
+    if (!on_dev && opts->mode == RIROS_MODE_TWO_D && d->twod.ctr) {
+        uint32_t words[8];
+        HIP_TRY(hipMemcpyAsync(words, d->twod.ctr, sizeof words, hipMemcpyDeviceToHost, s), "counter read");
+        HIP_TRY(hipStreamSynchronize(s), "counter sync");
+        if (words[5]) return set_err(RIROS_EDEVICE, "a handed-over fault was never published");
+    }
     riros_coverage* cov_dst = on_dev ? cov : d->d_cov;
     if (cov) HIP_TRY(riros::launch_coverage(d_detect, d_events, F, T, cov_dst, s), "coverage");
     if (!on_dev) {

@@ -1,13 +1,496 @@
+// Two-dimensional fault simulation (the paper's two-dimensional parallelism,
+// Sec. III and IV-C, transposed for a GPU).  Two persistent launches; every
+// wavefront takes work from atomic queues:
+//   launch A, phase 1: heavy faults placed up front (largest predicted load
+//      first), one fault per wavefront, each level's divergent frontier split
+//      across the lanes (wave_sim_fault, the structural dimension);
+//   launch A, phase 2: light faults, one per lane, each lane walking its own
+//      fault's frontier at its own cycle and taking a new fault when it
+//      finishes (the fault dimension).  A lane hands its fault over to the
+//      structural path when the frontier outgrows the lane's capacity, or when
+//      the fault's events per cycle exceed a threshold (a monitor in the spirit
+//      of the paper's execution-time-share monitor, Sec. IV-C);
+//   launch B: the handed-over faults, one per wavefront, from cycle 0.
+// No wavefront ever waits for another.  Where a fault runs never changes its
+// result.
+#include <hipcub/hipcub.hpp>
+
+#include "device_common.hpp"
 #include "twod.hpp"
+#include "wave_fault.hpp"
 
 namespace riros {
 
-int run_twod(const DevDesign&, TwoDWorkspace&, const uint64_t*, uint32_t, const riros_fault*, const float*,
-             uint32_t, int, const TwoDParams&, uint32_t*, uint64_t*, hipEvent_t, hipEvent_t, hipStream_t,
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+struct TwoDCounters {
+    uint32_t light_head;   // next index into the light queue
+    uint32_t esc_count;    // faults handed from light lanes to the heavy path
+    uint32_t heavy_head;   // next index into the up-front heavy queue
+    uint32_t n_heavy;      // faults placed on the heavy queue up front
+    uint32_t esc_head;     // next handed-over fault to simulate
+    uint32_t error;        // set if a handed-over fault was never published
+    uint32_t pad[2];
+};
+
+// Lane-private sets, held in registers: every index below is a compile-time
+// constant after unrolling, so no array leaves the register file.
+template <int C>
+struct SortedIds {
+    uint32_t v[C];
+    uint32_t n;
+    // Insert keeping ascending order; duplicates are dropped.  false = full.
+    __device__ __forceinline__ bool insert(uint32_t u)
+    {
+        bool dup = false;
+#pragma unroll
+        for (int k = 0; k < C; ++k) dup |= ((uint32_t)k < n) && v[k] == u;
+        if (dup) return true;
+        if (n >= (uint32_t)C) return false;
+        uint32_t x = u;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            if ((uint32_t)k < n) {
+                if (v[k] > x) {
+                    const uint32_t tmp = v[k];
+                    v[k] = x;
+                    x = tmp;
+                }
+            } else if ((uint32_t)k == n) {
+                v[k] = x;
+            }
+        }
+        n++;
+        return true;
+    }
+    __device__ __forceinline__ uint32_t pop_min()
+    {
+        const uint32_t u = v[0];
+#pragma unroll
+        for (int k = 0; k + 1 < C; ++k) v[k] = v[k + 1];
+        n--;
+        return u;
+    }
+};
+
+// (node id, faulty ^ golden) pairs.
+template <int C>
+struct DeltaSet {
+    uint32_t id[C];
+    uint64_t dx[C];
+    uint32_t n;
+    __device__ __forceinline__ bool add(uint32_t i, uint64_t x)
+    {
+        if (n >= (uint32_t)C) return false;
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            if ((uint32_t)k == n) {
+                id[k] = i;
+                dx[k] = x;
+            }
+        n++;
+        return true;
+    }
+    __device__ __forceinline__ uint64_t find(uint32_t i, bool& hit) const
+    {
+        uint64_t r = 0;
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            if (((uint32_t)k < n) && id[k] == i) {
+                r = dx[k];
+                hit = true;
+            }
+        return r;
+    }
+};
+
+__device__ __forceinline__ uint32_t pick4(uint32_t k, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+
+// Phase 2: light faults one per lane.  A lane with no divergent register
+// skips straight to the next cycle in which its site is excited (the site's
+// bit differs from the stuck value), reading 64 cycles of that bit with one
+// load of its bit-plane; only the site can diverge in such a cycle, with
+// faulty = golden ^ (1 << bit).  Otherwise the lane evaluates its pending
+// nodes in increasing id order (a topological order) from the node-major
+// golden values of the operands xor their divergence deltas.
+template <int C>
+__device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riros_fault* __restrict__ faults,
+                            uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
+                            uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
+                            uint64_t* __restrict__ events_out, uint32_t lanes, uint32_t rate_num)
+{
+    constexpr int CR = C / 2;
+    constexpr uint32_t kPre = 4;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t T = gw.T, TW = gw.TW;
+    const uint64_t* __restrict__ Gn = gw.Gn;
+    const uint64_t* __restrict__ Bp = gw.Bp;
+
+    uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, t = 0, det = RIROS_UNDETECTED;
+    uint64_t ev = 0;
+    bool in_cycle = false;
+    uint64_t exw = 0;
+    uint32_t ewb = kNone;
+    size_t bprow = 0;
+    NodeRec srec{};
+    uint32_t sf0 = 0, sf1 = 0, sf2 = 0, sf3 = 0;
+    bool exhausted = nlight == 0;
+    SortedIds<C> pend;
+    DeltaSet<C> div;
+    DeltaSet<CR> rcur, rnxt;
+    pend.n = div.n = rcur.n = rnxt.n = 0;
+
+    for (;;) {
+        // Refill idle lanes from the light queue (one atomic per wave); only
+        // the first `lanes` lanes take work, so that light faults spread over
+        // every wavefront of the grid.
+        const bool need = fi == kNone && lane < lanes;
+        const uint64_t needm = __ballot(need && !exhausted);
+        if (needm) {
+            const uint32_t k = (uint32_t)__popcll(needm);
+            const int leader = __ffsll((unsigned long long)needm) - 1;
+            uint32_t base = 0;
+            if ((int)lane == leader) base = atomicAdd(&ctr->light_head, k);
+            base = __shfl(base, leader, 64);
+            if (base + k >= nlight) exhausted = true;
+            if (need) {
+                const uint32_t idx = base + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
+                if (idx < nlight) {
+                    fi = lorder ? lorder[idx] : idx;
+                    const riros_fault f = faults[fi];
+                    site = d.u2i[f.site];
+                    fbit = f.bit;
+                    fval = f.stuck;
+                    srec = d.rec[site];
+                    bprow = (size_t)(d.bp_off[site] + fbit) * TW;
+                    const uint32_t nf = srec.fo1 - srec.fo0;
+                    sf0 = nf > 0 ? d.fo[srec.fo0] : 0;
+                    sf1 = nf > 1 ? d.fo[srec.fo0 + 1] : 0;
+                    sf2 = nf > 2 ? d.fo[srec.fo0 + 2] : 0;
+                    sf3 = nf > 3 ? d.fo[srec.fo0 + 3] : 0;
+                    t = 0;
+                    det = RIROS_UNDETECTED;
+                    ev = 0;
+                    pend.n = div.n = rcur.n = rnxt.n = 0;
+                    in_cycle = false;
+                    ewb = kNone;
+                }
+            }
+        }
+        if (__ballot(fi != kNone) == 0) break;
+        if (fi == kNone) continue;
+
+        bool esc_now = false;
+        // Record a divergent node: keep its delta, schedule its users, stage
+        // register next states, note output mismatches.
+        auto on_divergent = [&](uint32_t n, uint64_t delta, const NodeRec& r, uint32_t p0, uint32_t p1,
+                                uint32_t p2, uint32_t p3) {
+            if (!div.add(n, delta)) { esc_now = true; return; }
+            if ((r.flags & DF_PO) && det == RIROS_UNDETECTED) det = t;
+            for (uint32_t e = r.fo0; e < r.fo1; ++e) {
+                const uint32_t k = e - r.fo0;
+                const uint32_t u = k < kPre ? pick4(k, p0, p1, p2, p3) : d.fo[e];
+                if (!pend.insert(u)) { esc_now = true; return; }
+            }
+            for (uint32_t e = r.rfo0; e < r.rfo1; ++e)
+                if (!rnxt.add(d.rfo[e], delta)) { esc_now = true; return; }
+        };
+
+        bool evaluated = false;
+        if (!in_cycle) {
+            if (rcur.n == 0) {
+                // Skip to the next cycle in which the site is excited.
+                bool found = false;
+                while (t < T) {
+                    const uint32_t wb = t >> 6;
+                    if (wb != ewb) {
+                        uint64_t w = Bp[bprow + wb];
+                        if (fval) w = ~w;
+                        const uint32_t valid = T - (wb << 6);
+                        if (valid < 64) w &= (1ull << valid) - 1ull;
+                        exw = w;
+                        ewb = wb;
+                    }
+                    const uint64_t m = exw >> (t & 63);
+                    if (m) {
+                        t += (uint32_t)__builtin_ctzll(m);
+                        found = true;
+                        break;
+                    }
+                    t = (wb + 1) << 6;
+                }
+                if (!found) {
+                    detect_out[fi] = det;
+                    if (events_out) events_out[fi] = ev;
+                    fi = kNone;
+                    continue;
+                }
+                ev++;
+                on_divergent(site, 1ull << fbit, srec, sf0, sf1, sf2, sf3);
+                evaluated = true;
+            } else {
+#pragma unroll
+                for (int k = 0; k < CR; ++k)
+                    if ((uint32_t)k < rcur.n) (void)pend.insert(rcur.id[k]);
+                if (!pend.insert(site)) esc_now = true;
+            }
+            in_cycle = true;
+        }
+        if (!evaluated && !esc_now) {
+            // Evaluate the lowest pending node (users always have larger ids).
+            const uint32_t n = pend.pop_min();
+            const NodeRec r = d.rec[n];
+            const uint64_t gv = Gn[(size_t)n * T + t];
+            const uint32_t nf = r.fo1 - r.fo0;
+            const uint32_t p0 = nf > 0 ? d.fo[r.fo0] : 0;
+            const uint32_t p1 = nf > 1 ? d.fo[r.fo0 + 1] : 0;
+            const uint32_t p2 = nf > 2 ? d.fo[r.fo0 + 2] : 0;
+            const uint32_t p3 = nf > 3 ? d.fo[r.fo0 + 3] : 0;
+            uint64_t delta = 0;
+            bool din = false;
+            if (r.op == RIROS_OP_REG) {
+                delta = rcur.find(n, din);
+            } else if (r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST) {
+                const int ar = dev_arity(r.op);
+                const uint32_t ins[3] = {r.a, r.b, r.c};
+                uint64_t xs[3] = {0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < ar) xs[k] = Gn[(size_t)ins[k] * T + t];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < ar) xs[k] ^= div.find(ins[k], din);
+                delta = apply_opw(r.op, r.width, r.b, r.c, xs[0], xs[1], xs[2]) ^ gv;
+            }
+            if (n == site) delta = force_bit(gv ^ delta, fbit, fval) ^ gv;
+            const bool dout = delta != 0;
+            if (din || dout) ev++;
+            if (dout) on_divergent(n, delta, r, p0, p1, p2, p3);
+        }
+
+        // Monitor: a fault averaging more than rate_num/4 events per cycle after
+        // its first 8 cycles belongs on the structural path.
+        if (!esc_now && rate_num && t >= 8 && ev * 4 > (uint64_t)rate_num * (t + 1)) esc_now = true;
+        if (esc_now) {
+            const uint32_t slot = atomicAdd(&ctr->esc_count, 1u);
+            esc[slot] = fi;
+            fi = kNone;
+            continue;
+        }
+        if (in_cycle && pend.n == 0) {
+            // End of cycle t.
+            bool done = drop && det != RIROS_UNDETECTED;
+            if (!done) {
+                t++;
+                div.n = 0;
+                rcur = rnxt;
+                rnxt.n = 0;
+                in_cycle = false;
+                done = t >= T;
+            }
+            if (done) {
+                detect_out[fi] = det;
+                if (events_out) events_out[fi] = ev;
+                fi = kNone;
+            }
+        }
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(64) void k_twod_a(DevDesign d, GoldenView gw, const riros_fault* __restrict__ faults,
+                                               uint32_t F, const uint32_t* __restrict__ order, TwoDCounters* ctr,
+                                               uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
+                                               uint32_t rate_num, uint32_t* __restrict__ detect_out,
+                                               uint64_t* __restrict__ events_out)
+{
+    extern __shared__ uint32_t lds[];
+    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
+    wave_lds_clear(s, d.N, d.L, d.R);
+    __syncthreads();
+    Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
+    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * d.R;
+    uint64_t stamp0 = ws.stamp_base;
+    const uint32_t nh = ctr->n_heavy;
+    // Phase 1: heavy faults placed up front.
+    for (;;) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= nh) break;
+        const uint32_t fi = order ? order[idx] : idx;
+        uint32_t det;
+        uint64_t ev;
+        wave_sim_fault(d, gw.G, gw.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        if (threadIdx.x == 0) {
+            detect_out[fi] = det;
+            if (events_out) events_out[fi] = ev;
+        }
+    }
+    // Phase 2: light faults, one per lane; each wavefront takes at most its
+    // share of lanes so that light faults spread over every wavefront.
+    const uint32_t nlight = F - nh;
+    const uint32_t lanes = min(64u, max(1u, (nlight + gridDim.x - 1) / gridDim.x));
+    light_phase<C>(d, gw, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out, events_out,
+                   lanes, rate_num);
+}
+
+// Launch B: the faults handed over in launch A (their list is complete).
+__global__ __launch_bounds__(64) void k_twod_b(DevDesign d, GoldenView gw, const riros_fault* __restrict__ faults,
+                                               TwoDCounters* ctr, const uint32_t* __restrict__ esc, int drop,
+                                               PlainWorkspace ws, uint32_t* __restrict__ detect_out,
+                                               uint64_t* __restrict__ events_out)
+{
+    extern __shared__ uint32_t lds[];
+    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
+    wave_lds_clear(s, d.N, d.L, d.R);
+    __syncthreads();
+    Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
+    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * d.R;
+    uint64_t stamp0 = ws.stamp_base;
+    const uint32_t n = ctr->esc_count;
+    for (;;) {
+        uint32_t idx = 0;
+        if (threadIdx.x == 0) idx = atomicAdd(&ctr->esc_head, 1u);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= n) break;
+        const uint32_t fi = esc[idx];
+        uint32_t det;
+        uint64_t ev;
+        wave_sim_fault(d, gw.G, gw.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        if (threadIdx.x == 0) {
+            detect_out[fi] = det;
+            if (events_out) events_out[fi] = ev;
+        }
+    }
+}
+
+// Order: fault indexes sorted by descending priority; the prefix with
+// priority > theta is the up-front heavy queue.
+__global__ void k_iota(uint32_t* __restrict__ v, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ v, uint32_t n, uint32_t x)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = x;
+}
+
+__global__ void k_count_heavy(const float* __restrict__ sorted_desc, uint32_t n, float theta, TwoDCounters* ctr)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const bool h = sorted_desc[i] > theta;
+        const bool next_h = (i + 1 < n) && sorted_desc[i + 1] > theta;
+        if (h && !next_h) ctr->n_heavy = i + 1;
+    }
+}
+
+__global__ void k_zero_counters(TwoDCounters* ctr)
+{
+    if (threadIdx.x < sizeof(TwoDCounters) / 4) ((uint32_t*)ctr)[threadIdx.x] = 0;
+}
+
+struct TwoDLayout {
+    size_t ctr, esc, order, idx, keys_out, temp, total;
+    size_t temp_bytes;
+};
+
+static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    TwoDLayout l{};
+    size_t o = 0;
+    l.ctr = o; o += up(sizeof(TwoDCounters));
+    l.esc = o; o += up((size_t)F * 4);
+    l.order = o; o += up((size_t)F * 4);
+    l.idx = o; o += up((size_t)F * 4);
+    l.keys_out = o; o += up((size_t)F * 4);
+    l.temp = o; o += up(temp_bytes);
+    l.total = o;
+    l.temp_bytes = temp_bytes;
+    return l;
+}
+
+template <int C>
+static hipError_t launch_twod_c(const DevDesign& d, const GoldenView& gw, const riros_fault* faults, uint32_t F,
+                                const uint32_t* order, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                const PlainWorkspace& ws, uint32_t blocks, uint32_t rate_num, uint32_t* detect,
+                                uint64_t* events, hipStream_t s)
+{
+    const size_t lds = wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
+    hipError_t e = hipFuncSetAttribute((const void*)k_twod_a<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_twod_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_twod_a<C>, dim3(blocks), dim3(64), lds, s, d, gw, faults, F, order, ctr, esc, drop, ws,
+                       rate_num, detect, events);
+    PlainWorkspace wsb = ws;
+    wsb.stamp_base = ws.stamp_base + (uint64_t)F * gw.T + 1;
+    hipLaunchKernelGGL(k_twod_b, dim3(blocks), dim3(64), lds, s, d, gw, faults, ctr, esc, drop, wsb, detect,
+                       events);
+    return hipGetLastError();
+}
+
+int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const riros_fault* faults,
+             const float* priority, uint32_t F, int drop, const TwoDParams& p, PlainWorkspace heavy_ws,
+             uint32_t blocks, uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
              std::string& err)
 {
-    err = "two-dimensional mode is not available in this build";
-    return RIROS_EINVAL;
+    size_t temp_bytes = 0;
+    if (priority) {
+        hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, temp_bytes, (const float*)nullptr,
+                                                                   (float*)nullptr, (const uint32_t*)nullptr,
+                                                                   (uint32_t*)nullptr, (int)F, 0, 32, s);
+        if (e != hipSuccess) { err = "sort size query failed"; return RIROS_EDEVICE; }
+    }
+    const TwoDLayout lay = layout_for(F, temp_bytes);
+    if (ws.bytes < lay.total) {
+        if (ws.mem) (void)hipFree(ws.mem);
+        ws.mem = nullptr;
+        ws.bytes = 0;
+        if (hipMalloc(&ws.mem, lay.total) != hipSuccess) { err = "two-dimensional workspace allocation"; return RIROS_ENOMEM; }
+        ws.bytes = lay.total;
+    }
+    char* base = (char*)ws.mem;
+    TwoDCounters* ctr = (TwoDCounters*)(base + lay.ctr);
+    uint32_t* esc = (uint32_t*)(base + lay.esc);
+    uint32_t* order = nullptr;
+    ws.ctr = ctr;
+
+    if (hipEventRecord(ev0, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
+    if (priority) {
+        uint32_t* idx = (uint32_t*)(base + lay.idx);
+        float* keys_out = (float*)(base + lay.keys_out);
+        order = (uint32_t*)(base + lay.order);
+        hipLaunchKernelGGL(k_iota, dim3((F + 255) / 256), dim3(256), 0, s, idx, F);
+        size_t tb = lay.temp_bytes;
+        hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, priority, keys_out, idx,
+                                                                   order, (int)F, 0, 32, s);
+        if (e != hipSuccess) { err = "priority sort failed"; return RIROS_EDEVICE; }
+        if (!(p.theta > 3.0e38f))
+            hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, p.theta, ctr);
+    }
+    hipError_t e;
+    const uint32_t rate_num = p.monitor_rate > 0.f ? (uint32_t)std::min(4.0e9f, p.monitor_rate * 4.f + 0.5f) : 0u;
+    switch (p.light_cap) {
+    case 4: e = launch_twod_c<4>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
+    case 16: e = launch_twod_c<16>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
+    case 0:
+    case 8: e = launch_twod_c<8>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
+    default: err = "light_cap must be 4, 8 or 16"; return RIROS_EINVAL;
+    }
+    if (e != hipSuccess) { err = std::string("two-dimensional kernel: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
+    if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
+    return RIROS_OK;
 }
 
 void twod_free(TwoDWorkspace& ws)
@@ -15,6 +498,7 @@ void twod_free(TwoDWorkspace& ws)
     if (ws.mem) (void)hipFree(ws.mem);
     ws.mem = nullptr;
     ws.bytes = 0;
+    ws.ctr = nullptr;
 }
 
 }  // namespace riros

@@ -1,0 +1,201 @@
+// One faulty machine simulated by one wavefront, the divergent frontier of
+// each level split across the 64 lanes (structural parallelism of the paper,
+// Sec. IV-C, applied to a single fault).
+#pragma once
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace riros {
+
+constexpr uint32_t kListCap = 2048;
+
+// LDS of one wave: sched[N/32] nodes to evaluate this cycle; lvlm[L/32]
+// levels holding scheduled nodes; rcur/rnext[R/32] registers whose state
+// diverges in this / the next cycle; list[kListCap] compacted node ids; flags.
+struct WaveLds {
+    uint32_t* sched;
+    uint32_t* lvlm;
+    uint32_t* rcur;
+    uint32_t* rnext;
+    uint32_t* list;
+    uint32_t* flags;
+};
+
+__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R)
+{
+    return (size_t)(N + 31) / 32 + (L + 31) / 32 + 2 * ((R + 31) / 32) + kListCap + 4;
+}
+
+__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R)
+{
+    const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
+    WaveLds s;
+    s.sched = base;
+    s.lvlm = s.sched + W;
+    s.rcur = s.lvlm + WL;
+    s.rnext = s.rcur + WR;
+    s.list = s.rnext + WR;
+    s.flags = s.list + kListCap;
+    return s;
+}
+
+__device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, uint32_t R)
+{
+    const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t i = lane; i < W; i += 64) s.sched[i] = 0;
+    for (uint32_t i = lane; i < WL; i += 64) s.lvlm[i] = 0;
+    for (uint32_t i = lane; i < 2 * WR; i += 64) s.rcur[i] = 0;
+}
+
+// Simulate fault f from cycle 0 (drop: stop after the detect cycle).  slots
+// is this wave's [N] faulty-value array, regs its [2][R] register next-state
+// ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform) and the
+// event count (wave total).  Must be called by all 64 lanes of a one-wave
+// workgroup (it uses __syncthreads as the wave's LDS fence).
+__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ G, uint32_t T,
+                                      const riros_fault f, int drop, const WaveLds& s,
+                                      Slot* __restrict__ slots, uint64_t* __restrict__ regs,
+                                      uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
+{
+    const uint32_t N = d.N, R = d.R;
+    const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t site = d.u2i[f.site];
+    const uint32_t site_lvl = d.level[site];
+    const uint32_t fbit = f.bit, fval = f.stuck;
+    for (uint32_t i = lane; i < WR; i += 64) s.rnext[i] = 0;
+    uint32_t ev = 0;
+    uint32_t det = RIROS_UNDETECTED;
+    __syncthreads();
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint64_t stamp = stamp0 + t + 1;
+        const uint64_t* g = G + (size_t)t * N;
+        const uint64_t* rst = regs + (size_t)(t & 1) * R;
+        uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
+        // Cycle start: registers whose D diverged last cycle are scheduled.
+        uint32_t any = 0;
+        for (uint32_t i = lane; i < WR; i += 64) {
+            const uint32_t m = s.rnext[i];
+            s.rcur[i] = m;
+            s.rnext[i] = 0;
+            s.sched[i] |= m;
+            any |= m;
+        }
+        const bool anyreg = __ballot(any != 0) != 0;
+        if (lane == 0) s.flags[0] = 0;
+        __syncthreads();
+        if (lane == 0) {
+            s.sched[site >> 5] |= 1u << (site & 31);
+            s.lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
+            if (anyreg) s.lvlm[0] |= 1u;
+        }
+        __syncthreads();
+        for (;;) {
+            // Lowest level with scheduled nodes (users are always at higher levels).
+            int lv = -1;
+            for (uint32_t wb = 0; wb < WL; wb += 64) {
+                const uint32_t w = wb + lane;
+                const uint32_t m = w < WL ? s.lvlm[w] : 0u;
+                const uint64_t bal = __ballot(m != 0);
+                if (bal) {
+                    const int first = __ffsll((unsigned long long)bal) - 1;
+                    const uint32_t mw = __shfl(m, first, 64);
+                    lv = (int)((wb + first) * 32 + __ffs(mw) - 1);
+                    break;
+                }
+            }
+            if (lv < 0) break;
+            __syncthreads();
+            if (lane == 0) s.lvlm[lv >> 5] &= ~(1u << (lv & 31));
+            const uint32_t lo = d.lvl_off[lv], hi = d.lvl_off[lv + 1];
+            const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5;
+            for (uint32_t wb = w0; wb <= w1; wb += 64) {
+                const uint32_t w = wb + lane;
+                uint32_t bits = 0;
+                if (w <= w1) {
+                    uint32_t m = ~0u;
+                    if (w == w0) m &= ~0u << (lo & 31);
+                    if (w == w1 && (hi & 31)) m &= (1u << (hi & 31)) - 1u;
+                    const uint32_t word = s.sched[w];
+                    bits = word & m;
+                    if (bits) s.sched[w] = word & ~m;
+                }
+                const uint32_t cnt = __popc(bits);
+                const uint32_t incl = wave_incl_scan(cnt);
+                const uint32_t total = __shfl(incl, 63, 64);
+                uint32_t off = incl - cnt;
+                while (bits) {
+                    const int b = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    s.list[off++] = w * 32 + (uint32_t)b;
+                }
+                __syncthreads();
+                for (uint32_t i = lane; i < total; i += 64) {
+                    const uint32_t n = s.list[i];
+                    // Record (descriptor + fan-out ranges) and the node's golden value in one round trip,
+                    // then operands and the first fan-out entries in a second.
+                    const NodeRec x = d.rec[n];
+                    const uint64_t gv = g[n];
+                    const uint32_t nf = x.fo1 - x.fo0;
+                    const uint64_t pk0 = nf > 0 ? d.fo_pk[x.fo0] : 0;
+                    const uint64_t pk1 = nf > 1 ? d.fo_pk[x.fo0 + 1] : 0;
+                    bool din = false;
+                    uint64_t v;
+                    if (x.op == RIROS_OP_REG) {
+                        din = (s.rcur[n >> 5] >> (n & 31)) & 1u;
+                        v = din ? rst[n] : gv;
+                    } else if (x.op == RIROS_OP_PI || x.op == RIROS_OP_CONST) {
+                        v = gv;
+                    } else {
+                        const int ar = dev_arity(x.op);
+                        uint64_t xs[3] = {0, 0, 0};
+                        const uint32_t ins[3] = {x.a, x.b, x.c};
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            if (k < ar) {
+                                const Slot sl = slots[ins[k]];
+                                const uint64_t gx = g[ins[k]];
+                                const bool dv = sl.stamp == stamp;
+                                xs[k] = dv ? sl.v : gx;
+                                din |= dv;
+                            }
+                        }
+                        v = apply_opw(x.op, x.width, x.b, x.c, xs[0], xs[1], xs[2]);
+                    }
+                    if (n == site) v = force_bit(v, fbit, fval);
+                    const bool dout = v != gv;
+                    ev += (din || dout) ? 1u : 0u;
+                    if (dout) {
+                        Slot sl;
+                        sl.v = v;
+                        sl.stamp = stamp;
+                        slots[n] = sl;
+                        if (x.flags & DF_PO) s.flags[0] = 1;
+                        for (uint32_t e = x.fo0; e < x.fo1; ++e) {
+                            const uint64_t pk = e == x.fo0 ? pk0 : (e == x.fo0 + 1 ? pk1 : d.fo_pk[e]);
+                            const uint32_t c = (uint32_t)pk, lc = (uint32_t)(pk >> 32);
+                            atomicOr(&s.sched[c >> 5], 1u << (c & 31));
+                            atomicOr(&s.lvlm[lc >> 5], 1u << (lc & 31));
+                        }
+                        for (uint32_t e = x.rfo0; e < x.rfo1; ++e) {
+                            const uint32_t r = d.rfo[e];
+                            rnx[r] = v;
+                            atomicOr(&s.rnext[r >> 5], 1u << (r & 31));
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (s.flags[0] && det == RIROS_UNDETECTED) det = t;
+        __syncthreads();
+        if (drop && det != RIROS_UNDETECTED) break;
+    }
+    stamp0 += T;
+    det_out = det;
+    ev_out = wave_sum_u64((uint64_t)ev);
+}
+
+}  // namespace riros

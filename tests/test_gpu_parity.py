@@ -13,7 +13,7 @@ from paper_2508_16376_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 UND = riros.UNDETECTED
-MODES = [riros.MODE_PLAIN]
+MODES = [riros.MODE_PLAIN, riros.MODE_TWO_D]
 
 
 def _run(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, **kw):
@@ -135,11 +135,12 @@ def test_no_registers_and_register_chain(mode):
     _check(d, stim, T, all_faults(d), mode, variant=0)
 
 
-def test_faults_in_any_order_give_the_same_results(small):
+@pytest.mark.parametrize("mode", MODES)
+def test_faults_in_any_order_give_the_same_results(small, mode):
     w = small
     perm = np.argsort(W.counter_values(5, 0, w.faults.size))
-    det, ev, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults)
-    det2, ev2, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults[perm])
+    det, ev, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults, mode)
+    det2, ev2, _, _, _ = _run(w.design, w.stimulus, w.T, w.faults[perm], mode)
     np.testing.assert_array_equal(det[perm], det2)
     np.testing.assert_array_equal(ev[perm], ev2)
 
@@ -150,8 +151,8 @@ def test_repeated_calls_reuse_workspace(small):
     d = riros.Design(w.design)
     g = riros.Golden(d, w.stimulus, w.T)
     first = riros.fault_sim(d, g, w.faults)
-    for wpc in (1, 4, 16):
-        again = riros.fault_sim(d, g, w.faults, waves_per_cu=wpc)
+    for wpc, mode in ((1, 0), (4, 1), (16, 0), (2, 1)):
+        again = riros.fault_sim(d, g, w.faults, waves_per_cu=wpc, mode=mode)
         np.testing.assert_array_equal(first[0], again[0])
         np.testing.assert_array_equal(first[1], again[1])
 
@@ -196,3 +197,58 @@ def test_device_io_matches_host_io(small):
     np.testing.assert_array_equal(ev_dev.cpu().numpy().view(np.uint64), ev)
     c = cov_dev.cpu().numpy()
     assert list(c) == [cov["detected"], cov["total"], cov["fault_cycles"], cov["events"]]
+
+
+@pytest.mark.parametrize("light_cap", [4, 8, 16])
+def test_two_d_light_capacity_does_not_change_results(small, light_cap):
+    """Smaller capacities hand more faults to the heavy path; results are identical."""
+    _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, light_cap=light_cap)
+
+
+@pytest.mark.parametrize("theta", [float("-inf"), 0.25, 0.5, 0.9, float("inf")])
+def test_two_d_priority_and_threshold(small, theta):
+    """Random priorities: any order and any light/heavy split give identical results."""
+    prio = (W.counter_values(11, 0, small.faults.size) >> np.uint64(40)).astype(np.float32) / np.float32(1 << 24)
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop,
+               priority=prio, theta=theta)
+
+
+@pytest.mark.parametrize("rate", [0.5, 2.0, 8.0])
+def test_two_d_monitor_hand_over(small, rate):
+    """The events-per-cycle monitor moves faults to the structural path; results are identical."""
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, monitor_rate=rate)
+
+
+def test_two_d_rejects_bad_options(tiny):
+    d = riros.Design(tiny.design)
+    g = riros.Golden(d, tiny.stimulus, tiny.T)
+    for kw in ({"chunk": 3}, {"monitor_rate": -1.0}, {"light_cap": 5}):
+        with pytest.raises(riros.RirosError):
+            riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
+
+
+def test_two_d_waves_per_cu(small):
+    for wpc in (1, 3):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, waves_per_cu=wpc)
+
+
+def test_two_d_device_io_with_priority(small):
+    import torch
+    w = small
+    d = riros.Design(w.design)
+    g = riros.Golden(d, w.stimulus, w.T)
+    det, ev, cov = riros.fault_sim(d, g, w.faults)
+    dev = torch.device("cuda:0")
+    prio = torch.from_numpy((np.arange(w.faults.size) % 97).astype(np.float32)).to(dev)
+    f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
+    det_dev = torch.empty(w.faults.size, dtype=torch.int32, device=dev)
+    ev_dev = torch.empty(w.faults.size, dtype=torch.int64, device=dev)
+    cov_dev = torch.zeros(4, dtype=torch.int64, device=dev)
+    opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=torch.cuda.current_stream(), priority=prio,
+                           theta=90.0)
+    riros.fault_sim_device(d, g, f_dev, w.faults.size, det_dev, ev_dev, cov_dev, opts)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(det_dev.cpu().numpy().view(np.uint32), det)
+    np.testing.assert_array_equal(ev_dev.cpu().numpy().view(np.uint64), ev)
