@@ -440,6 +440,30 @@ def gen_faults(seed: int, d: Design, F: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Initial weights of the load predictor (an input of training)
+# ---------------------------------------------------------------------------
+
+MLP_SHAPES = [(64, 6), (64,), (64, 64), (64,), (64,), (1,)]   # W1 b1 W2 b2 W3 b3
+
+
+def mlp_init_weights(seed: int) -> np.ndarray:
+    """He-uniform initial weights (zero biases) for the 6-64-64-1 predictor, as
+    one float32 vector W1, b1, W2, b2, W3, b3 drawn from counter stream ``seed``."""
+    parts = []
+    ctr = 0
+    fan_in = {0: 6, 2: 64, 4: 64}
+    for k, shp in enumerate(MLP_SHAPES):
+        n = int(np.prod(shp))
+        if k in fan_in:
+            u = (counter_values(seed, ctr, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+            ctr += n
+            parts.append((2.0 * u - 1.0) * np.sqrt(6.0 / fan_in[k]))
+        else:
+            parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
 # The named workloads
 # ---------------------------------------------------------------------------
 
