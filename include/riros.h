@@ -162,6 +162,56 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
                     const riros_sim_opts* opts, uint32_t* detect, uint64_t* events,
                     riros_coverage* cov);
 
+/* ------------------------------------------------------------------------ */
+/* Learned load predictor.  It only orders faults and picks their starting   */
+/* path (the paper marks high-load nodes with an execution-time monitor,      */
+/* Sec. IV-C; here a small network predicts each fault's load up front), so   */
+/* no result depends on it.                                                   */
+/* ------------------------------------------------------------------------ */
+
+#define RIROS_NUM_FEATURES 6
+#define RIROS_MLP_PARAMS 4673          /* 6-64-64-1: W1[64][6] b1[64] W2[64][64] b2[64] W3[64] b3 */
+#define RIROS_MLP_WEIGHTS (4673 + 12)  /* parameters, then input mean[6] and std[6] */
+
+/* Per-fault features, float32[F][6]: log2(1 + forward combinational cone of
+ * the site, registers fed counted but not crossed, capped at 1024); site
+ * level / deepest level; fewest registers from the site to an output (capped
+ * at 16, -1 if none); log2(site width); toggle rate of the site bit over the
+ * golden trace (changes / (T-1)); fraction of cycles in which the site bit
+ * differs from the stuck value.  faults/out are device pointers when
+ * io_on_device (asynchronous on stream), else host pointers.  Errors as for
+ * riros_fault_sim. */
+int riros_features(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F, float* out,
+                   int32_t io_on_device, void* stream);
+
+typedef struct {
+    uint32_t epochs;   /* passes over the samples, in the given order */
+    uint32_t batch;    /* minibatch size (the last one of a pass may be smaller) */
+    float lr, beta1, beta2, eps;   /* Adam (Kingma and Ba, 2015) */
+} riros_train_cfg;
+
+/* Train the predictor with minibatch Adam on mean squared error.  Host
+ * arrays: feats float32[S][6], y float32[S] (target, e.g. log2(1 + events)),
+ * weights float32[RIROS_MLP_WEIGHTS]: on entry the initial parameters (the
+ * normalisation part is ignored), on return the trained parameters with the
+ * mean and standard deviation of each feature over the samples.  losses
+ * (may be NULL) receives the loss of every step, epochs * ceil(S / batch)
+ * floats.  Errors: RIROS_EINVAL (S, epochs or batch zero, NULL pointers),
+ * RIROS_ENOMEM, RIROS_EDEVICE. */
+int riros_mlp_train(const float* feats, const float* y, uint32_t S, const riros_train_cfg* cfg, float* weights,
+                    float* losses, void* stream);
+
+/* Predicted load for F feature rows with trained weights.  feats/out are
+ * device pointers when io_on_device (asynchronous), else host pointers. */
+int riros_mlp_predict(const float* weights, const float* feats, uint32_t F, float* out, int32_t io_on_device,
+                      void* stream);
+
+/* Gradient of the mean squared error over one batch of B samples (host
+ * arrays; weights include the normalisation): grad float32[RIROS_MLP_PARAMS],
+ * loss float32[1].  The same kernels as training; for checking them. */
+int riros_mlp_grad(const float* weights, const float* feats, const float* y, uint32_t B, float* grad,
+                   float* loss, void* stream);
+
 /* Number of nodes, levels and registers of a loaded design. */
 int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels, uint32_t* num_regs);
 

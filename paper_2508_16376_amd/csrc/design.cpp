@@ -7,7 +7,10 @@
 #include "design.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <deque>
+#include <thread>
 
 namespace riros {
 
@@ -222,6 +225,73 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
     }
     img.bp_rows = rows;
     return RIROS_OK;
+}
+
+// Predictor graph features.  The cone of a node is the number of distinct
+// nodes reached through combinational users, registers fed counted but not
+// crossed, the node itself excluded, capped at kConeCap.  Register depth is a
+// 0-1 breadth-first search backwards from the outputs: crossing a register
+// from its output to its D input costs one.
+void node_features(const Image& img, std::vector<float>& out)
+{
+    const uint32_t N = img.N;
+    out.assign((size_t)N * 4, 0.f);
+    const float maxl = (float)std::max<uint32_t>(1, img.L - 1);
+    // register depth
+    const int INF = 1 << 30;
+    std::vector<int> dist(N, INF);
+    std::deque<uint32_t> dq;
+    for (uint32_t p : img.po) { dist[p] = 0; dq.push_back(p); }
+    while (!dq.empty()) {
+        const uint32_t u = dq.front();
+        dq.pop_front();
+        const Desc& x = img.desc[u];
+        if (x.op == RIROS_OP_REG) {
+            if (dist[u] + 1 < dist[x.a]) { dist[x.a] = dist[u] + 1; dq.push_back(x.a); }
+        } else if (op_is_comb(x.op)) {
+            const uint32_t ins[3] = {x.a, x.b, x.c};
+            for (int k = 0; k < op_arity(x.op); ++k)
+                if (dist[u] < dist[ins[k]]) { dist[ins[k]] = dist[u]; dq.push_front(ins[k]); }
+        }
+    }
+    // cones, in parallel over nodes
+    std::vector<uint32_t> cone(N, 0);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto work = [&](unsigned tid) {
+        std::vector<uint32_t> seen(N, 0), q;
+        q.reserve(kConeCap + 64);
+        uint32_t mark = 0;
+        for (uint32_t s = tid; s < N; s += nt) {
+            ++mark;
+            seen[s] = mark;
+            q.clear();
+            q.push_back(s);
+            uint32_t count = 0;
+            for (size_t h = 0; h < q.size() && count < kConeCap; ++h) {
+                const uint32_t u = q[h];
+                for (uint32_t e = img.fo_off[u]; e < img.fo_off[u + 1]; ++e) {
+                    const uint32_t c = img.fo[e];
+                    if (seen[c] != mark) { seen[c] = mark; ++count; q.push_back(c); }
+                }
+                for (uint32_t e = img.rfo_off[u]; e < img.rfo_off[u + 1]; ++e) {
+                    const uint32_t r = img.rfo[e];
+                    if (seen[r] != mark) { seen[r] = mark; ++count; }
+                }
+            }
+            cone[s] = std::min(count, kConeCap);
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& t : th) t.join();
+    for (uint32_t n = 0; n < N; ++n) {
+        float* o = &out[(size_t)n * 4];
+        o[0] = (float)std::log2(1.0 + (double)cone[n]);
+        o[1] = (float)img.level[n] / maxl;
+        o[2] = dist[n] >= INF ? -1.f : (float)std::min(dist[n], kDepthCap);
+        o[3] = (float)std::log2((double)img.desc[n].width);
+    }
 }
 
 }  // namespace riros

@@ -50,6 +50,13 @@ struct Image {
     uint32_t bp_rows = 0;                       // total bit-plane rows (sum of widths)
 };
 
+// Per-node graph features of the load predictor (internal numbering):
+// log2(1 + forward cone, capped), level / deepest level, fewest registers to
+// an output (capped, -1 when none), log2(width).
+constexpr uint32_t kConeCap = 1024;
+constexpr int kDepthCap = 16;
+void node_features(const Image& img, std::vector<float>& out /* [N][4] */);
+
 // Registers take internal ids 0..R-1, then the other level-0 nodes (PI,
 // CONST), then levels 1..L-1.  Returns RIROS_OK or an error code with `err`.
 int build_image(const riros_design_desc& desc, Image& img, std::string& err);

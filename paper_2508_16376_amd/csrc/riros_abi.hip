@@ -11,6 +11,7 @@
 
 #include "design.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "riros.h"
 #include "twod.hpp"
 
@@ -50,6 +51,17 @@ hipError_t dev_upload(T** dst, const std::vector<T>& src)
     return hipSuccess;
 }
 
+// Device buffer freed on scope exit.
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) { return hipMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T)); }
+};
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -85,6 +97,7 @@ struct riros_design_s {
     size_t stage_cap = 0;
     riros_coverage* d_cov = nullptr;
     uint32_t* d_bad = nullptr;
+    float4* d_nodefeat = nullptr;   // predictor graph features, computed on first use
 };
 
 struct riros_golden_s {
@@ -113,6 +126,7 @@ static void free_design_mem(riros_design d)
     if (d->stage) (void)hipFree(d->stage);
     if (d->d_cov) (void)hipFree(d->d_cov);
     if (d->d_bad) (void)hipFree(d->d_bad);
+    if (d->d_nodefeat) (void)hipFree(d->d_nodefeat);
     riros::twod_free(d->twod);
 }
 
@@ -420,6 +434,140 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
                          "coverage download");
         HIP_TRY(hipStreamSynchronize(s), "fault simulation sync");
     }
+    return RIROS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Load predictor
+// ---------------------------------------------------------------------------
+
+int riros_features(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F, float* out,
+                   int32_t io_on_device, void* stream)
+{
+    if (!d || !g) return set_err(RIROS_EINVAL, "NULL argument");
+    if (g->d != d) return set_err(RIROS_EINVAL, "golden trace belongs to another design");
+    if (F > 0 && (!faults || !out)) return set_err(RIROS_EINVAL, "faults or out is NULL");
+    DeviceGuard guard(d->device);
+    hipStream_t s = (hipStream_t)stream;
+    const riros::Image& im = d->img;
+    if (!d->d_nodefeat) {
+        std::vector<float> nf;
+        riros::node_features(im, nf);
+        HIP_TRY(hipMalloc((void**)&d->d_nodefeat, (size_t)im.N * sizeof(float4)), "feature allocation");
+        HIP_TRY(hipMemcpy(d->d_nodefeat, nf.data(), nf.size() * sizeof(float), hipMemcpyHostToDevice), "feature upload");
+    }
+    if (F == 0) return RIROS_OK;
+    if (io_on_device) {
+        HIP_TRY(hipMemsetAsync(d->d_bad, 0, sizeof(uint32_t), s), "validate clear");
+        HIP_TRY(riros::launch_validate_faults(d->dev, faults, F, d->d_bad, s), "validate launch");
+        uint32_t bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, d->d_bad, sizeof bad, hipMemcpyDeviceToHost, s), "validate read");
+        HIP_TRY(hipStreamSynchronize(s), "validate sync");
+        if (bad) return set_err(RIROS_EINVAL, std::to_string(bad) + " invalid faults in device fault list");
+        HIP_TRY(riros::launch_features(d->dev, g->view(), d->d_nodefeat, faults, F, out, s), "feature kernel");
+        return RIROS_OK;
+    }
+    for (uint32_t i = 0; i < F; ++i) {
+        const riros_fault& f = faults[i];
+        if (f.site >= im.N || f.stuck > 1 || f.bit >= im.desc[im.u2i[f.site]].width)
+            return set_err(RIROS_EINVAL, "invalid fault " + std::to_string(i));
+    }
+    DevBuf<riros_fault> df;
+    DevBuf<float> dout;
+    HIP_TRY(df.alloc(F), "allocation");
+    HIP_TRY(dout.alloc((size_t)F * riros::kMlpFeatures), "allocation");
+    HIP_TRY(hipMemcpyAsync(df.p, faults, (size_t)F * sizeof(riros_fault), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(riros::launch_features(d->dev, g->view(), d->d_nodefeat, df.p, F, dout.p, s), "feature kernel");
+    HIP_TRY(hipMemcpyAsync(out, dout.p, (size_t)F * riros::kMlpFeatures * sizeof(float), hipMemcpyDeviceToHost, s),
+            "download");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    return RIROS_OK;
+}
+
+int riros_mlp_train(const float* feats, const float* y, uint32_t S, const riros_train_cfg* cfg, float* weights,
+                    float* losses, void* stream)
+{
+    if (!feats || !y || !cfg || !weights) return set_err(RIROS_EINVAL, "NULL argument");
+    if (S == 0 || cfg->epochs == 0 || cfg->batch == 0) return set_err(RIROS_EINVAL, "S, epochs and batch must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t B = std::min(cfg->batch, S);
+    const uint32_t steps_per_epoch = (S + B - 1) / B;
+    DevBuf<float> dx, dy, dw, dm, dv, dpart, dlp, dloss;
+    HIP_TRY(dx.alloc((size_t)S * riros::kMlpFeatures), "allocation");
+    HIP_TRY(dy.alloc(S), "allocation");
+    HIP_TRY(dw.alloc(riros::kMlpWeights), "allocation");
+    HIP_TRY(dm.alloc(riros::kMlpParams), "allocation");
+    HIP_TRY(dv.alloc(riros::kMlpParams), "allocation");
+    HIP_TRY(dpart.alloc(riros::mlp_partial_floats(B)), "allocation");
+    HIP_TRY(dlp.alloc((B + 31) / 32 + 1), "allocation");
+    HIP_TRY(dloss.alloc((size_t)cfg->epochs * steps_per_epoch), "allocation");
+    HIP_TRY(hipMemcpyAsync(dx.p, feats, (size_t)S * riros::kMlpFeatures * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemcpyAsync(dy.p, y, (size_t)S * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemcpyAsync(dw.p, weights, riros::kMlpParams * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemsetAsync(dm.p, 0, riros::kMlpParams * sizeof(float), s), "clear");
+    HIP_TRY(hipMemsetAsync(dv.p, 0, riros::kMlpParams * sizeof(float), s), "clear");
+    HIP_TRY(riros::mlp_norm_stats(dx.p, S, dw.p, s), "normalisation");
+    const riros::MlpHyper h{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps};
+    uint32_t step = 0;
+    for (uint32_t e = 0; e < cfg->epochs; ++e)
+        for (uint32_t b0 = 0; b0 < S; b0 += B) {
+            const uint32_t nb = std::min(B, S - b0);
+            HIP_TRY(riros::mlp_step(dw.p, dx.p + (size_t)b0 * riros::kMlpFeatures, dy.p + b0, nb, dpart.p, dlp.p, dm.p,
+                                    dv.p, nullptr, dloss.p + step, step + 1, h, s),
+                    "training step");
+            ++step;
+        }
+    HIP_TRY(hipMemcpyAsync(weights, dw.p, riros::kMlpWeights * sizeof(float), hipMemcpyDeviceToHost, s), "download");
+    if (losses)
+        HIP_TRY(hipMemcpyAsync(losses, dloss.p, (size_t)step * sizeof(float), hipMemcpyDeviceToHost, s), "download");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    return RIROS_OK;
+}
+
+int riros_mlp_predict(const float* weights, const float* feats, uint32_t F, float* out, int32_t io_on_device,
+                      void* stream)
+{
+    if (!weights || (F > 0 && (!feats || !out))) return set_err(RIROS_EINVAL, "NULL argument");
+    if (F == 0) return RIROS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (io_on_device) {
+        HIP_TRY(riros::mlp_forward(weights, feats, F, out, s), "inference");
+        return RIROS_OK;
+    }
+    DevBuf<float> dw, dx, dout;
+    HIP_TRY(dw.alloc(riros::kMlpWeights), "allocation");
+    HIP_TRY(dx.alloc((size_t)F * riros::kMlpFeatures), "allocation");
+    HIP_TRY(dout.alloc(F), "allocation");
+    HIP_TRY(hipMemcpyAsync(dw.p, weights, riros::kMlpWeights * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemcpyAsync(dx.p, feats, (size_t)F * riros::kMlpFeatures * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(riros::mlp_forward(dw.p, dx.p, F, dout.p, s), "inference");
+    HIP_TRY(hipMemcpyAsync(out, dout.p, (size_t)F * sizeof(float), hipMemcpyDeviceToHost, s), "download");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    return RIROS_OK;
+}
+
+int riros_mlp_grad(const float* weights, const float* feats, const float* y, uint32_t B, float* grad, float* loss,
+                   void* stream)
+{
+    if (!weights || !feats || !y || !grad || !loss) return set_err(RIROS_EINVAL, "NULL argument");
+    if (B == 0) return set_err(RIROS_EINVAL, "empty batch");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> dw, dx, dy, dpart, dlp, dg, dl;
+    HIP_TRY(dw.alloc(riros::kMlpWeights), "allocation");
+    HIP_TRY(dx.alloc((size_t)B * riros::kMlpFeatures), "allocation");
+    HIP_TRY(dy.alloc(B), "allocation");
+    HIP_TRY(dpart.alloc(riros::mlp_partial_floats(B)), "allocation");
+    HIP_TRY(dlp.alloc((B + 31) / 32 + 1), "allocation");
+    HIP_TRY(dg.alloc(riros::kMlpParams), "allocation");
+    HIP_TRY(dl.alloc(1), "allocation");
+    HIP_TRY(hipMemcpyAsync(dw.p, weights, riros::kMlpWeights * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemcpyAsync(dx.p, feats, (size_t)B * riros::kMlpFeatures * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    HIP_TRY(hipMemcpyAsync(dy.p, y, (size_t)B * sizeof(float), hipMemcpyHostToDevice, s), "upload");
+    const riros::MlpHyper h{0.f, 0.f, 0.f, 0.f};
+    HIP_TRY(riros::mlp_step(dw.p, dx.p, dy.p, B, dpart.p, dlp.p, nullptr, nullptr, dg.p, dl.p, 1, h, s), "gradient");
+    HIP_TRY(hipMemcpyAsync(grad, dg.p, riros::kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s), "download");
+    HIP_TRY(hipMemcpyAsync(loss, dl.p, sizeof(float), hipMemcpyDeviceToHost, s), "download");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
     return RIROS_OK;
 }
 

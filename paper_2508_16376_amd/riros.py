@@ -28,7 +28,10 @@ MODE_TWO_D = 1
 
 EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros_free_golden",
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
-            "riros_last_error"]
+            "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad"]
+N_FEATURES = 6
+MLP_PARAMS = 4673
+MLP_WEIGHTS = MLP_PARAMS + 12
 
 
 class RirosError(RuntimeError):
@@ -47,6 +50,11 @@ class SimOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("priority", ctypes.c_void_p), ("theta", ctypes.c_float),
                 ("light_cap", ctypes.c_int32), ("chunk", ctypes.c_int32), ("monitor_rate", ctypes.c_float),
                 ("stream", ctypes.c_void_p)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class Coverage(ctypes.Structure):
@@ -107,6 +115,14 @@ def lib():
         L.riros_last_kernel_ms.restype = I
         L.riros_last_error.argtypes = []
         L.riros_last_error.restype = ctypes.c_char_p
+        L.riros_features.argtypes = [P, P, P, U, P, ctypes.c_int32, P]
+        L.riros_features.restype = I
+        L.riros_mlp_train.argtypes = [P, P, U, ctypes.POINTER(TrainCfg), P, P, P]
+        L.riros_mlp_train.restype = I
+        L.riros_mlp_predict.argtypes = [P, P, U, P, ctypes.c_int32, P]
+        L.riros_mlp_predict.restype = I
+        L.riros_mlp_grad.argtypes = [P, P, P, U, P, P, P]
+        L.riros_mlp_grad.restype = I
         _lib = L
     return _lib
 
@@ -229,3 +245,54 @@ def last_kernel_ms() -> float:
     ms = ctypes.c_float()
     _check(lib().riros_last_kernel_ms(ctypes.byref(ms)))
     return float(ms.value)
+
+
+def features(design: Design, golden: Golden, faults: np.ndarray) -> np.ndarray:
+    """riros_features on host arrays: float32[F][6]."""
+    fl = np.ascontiguousarray(faults)
+    out = np.empty((fl.size, N_FEATURES), dtype=np.float32)
+    _check(lib().riros_features(design.handle, golden.handle, _ptr(fl), fl.size, _ptr(out), 0, None))
+    return out
+
+
+def features_device(design: Design, golden: Golden, faults_dev, F: int, out_dev, stream=None):
+    _check(lib().riros_features(design.handle, golden.handle, _ptr(faults_dev), F, _ptr(out_dev), 1,
+                                _stream_ptr(stream)))
+
+
+def mlp_train(feats: np.ndarray, y: np.ndarray, init_params: np.ndarray, *, epochs=10, batch=4096, lr=1e-3,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+    """riros_mlp_train: returns (weights float32[MLP_WEIGHTS], per-step losses)."""
+    x = np.ascontiguousarray(feats, dtype=np.float32)
+    yy = np.ascontiguousarray(y, dtype=np.float32)
+    S = x.shape[0]
+    w = np.zeros(MLP_WEIGHTS, dtype=np.float32)
+    w[:MLP_PARAMS] = init_params[:MLP_PARAMS]
+    B = min(batch, S)
+    steps = epochs * ((S + B - 1) // B)
+    losses = np.empty(steps, dtype=np.float32)
+    cfg = TrainCfg(epochs, batch, lr, beta1, beta2, eps)
+    _check(lib().riros_mlp_train(_ptr(x), _ptr(yy), S, ctypes.byref(cfg), _ptr(w), _ptr(losses), None))
+    return w, losses
+
+
+def mlp_predict(weights: np.ndarray, feats: np.ndarray) -> np.ndarray:
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    x = np.ascontiguousarray(feats, dtype=np.float32)
+    out = np.empty(x.shape[0], dtype=np.float32)
+    _check(lib().riros_mlp_predict(_ptr(w), _ptr(x), x.shape[0], _ptr(out), 0, None))
+    return out
+
+
+def mlp_predict_device(weights_dev, feats_dev, F: int, out_dev, stream=None):
+    _check(lib().riros_mlp_predict(_ptr(weights_dev), _ptr(feats_dev), F, _ptr(out_dev), 1, _stream_ptr(stream)))
+
+
+def mlp_grad(weights: np.ndarray, feats: np.ndarray, y: np.ndarray):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    x = np.ascontiguousarray(feats, dtype=np.float32)
+    yy = np.ascontiguousarray(y, dtype=np.float32)
+    g = np.empty(MLP_PARAMS, dtype=np.float32)
+    loss = np.empty(1, dtype=np.float32)
+    _check(lib().riros_mlp_grad(_ptr(w), _ptr(x), _ptr(yy), x.shape[0], _ptr(g), _ptr(loss), None))
+    return g, float(loss[0])

@@ -1,0 +1,130 @@
+"""GPU parity of the load predictor: features, gradient, Adam step, inference
+and training against the float64 reference; and what ordering by the trained
+network changes (never a result)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import features as FT
+from oracle import mlp as RM
+from paper_2508_16376_amd import predictor, riros
+from paper_2508_16376_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    return W.medium(seed=909, F=3000, T=400, n_nodes=4000)
+
+
+def _weights_with_norm(params, mean, std):
+    w = np.zeros(riros.MLP_WEIGHTS, dtype=np.float32)
+    w[:riros.MLP_PARAMS] = params
+    w[riros.MLP_PARAMS:riros.MLP_PARAMS + 6] = mean
+    w[riros.MLP_PARAMS + 6:] = std
+    return w
+
+
+def _batch(seed, B):
+    r = (W.counter_values(seed, 0, B * 7) >> np.uint64(11)).astype(np.float64) / (1 << 53)
+    return (r[:B * 6].reshape(B, 6) * 8 - 2).astype(np.float32), (r[B * 6:] * 12).astype(np.float32)
+
+
+def test_features_match_reference(small):
+    d = riros.Design(small.design)
+    g = riros.Golden(d, small.stimulus, small.T)
+    got = riros.features(d, g, small.faults)
+    G = oracle.golden(small.design, small.stimulus, small.T)
+    ref = FT.features(small.design, G, small.faults)
+    np.testing.assert_allclose(got, ref, rtol=2e-6, atol=1e-6)
+
+
+def test_gradient_matches_reference():
+    p = W.mlp_init_weights(41)
+    mean = np.array([1, 2, 0, -1, 0.5, 3], dtype=np.float32)
+    std = np.array([2, 1, 3, 1, 0.5, 2], dtype=np.float32)
+    w = _weights_with_norm(p, mean, std)
+    for B in (1, 31, 32, 100, 257):
+        x, y = _batch(100 + B, B)
+        g, L = riros.mlp_grad(w, x, y)
+        xn = RM.normalise(x.astype(np.float64), mean.astype(np.float64), std.astype(np.float64))
+        Lr, gr = RM.grad(p.astype(np.float64), xn, y.astype(np.float64))
+        assert abs(L - Lr) <= 1e-5 * max(1.0, abs(Lr))
+        for a, b in zip(RM.unpack(g), RM.unpack(gr)):
+            a, b = np.atleast_1d(a), np.atleast_1d(b)
+            assert np.linalg.norm(a - b) <= 1e-4 * max(np.linalg.norm(b), 1e-12), B
+
+
+def test_one_adam_step_matches_reference():
+    p = W.mlp_init_weights(43)
+    x, y = _batch(7, 64)
+    w, losses = riros.mlp_train(x, y, p, epochs=1, batch=64, lr=1e-3)
+    mean, std = x.astype(np.float64).mean(axis=0), x.astype(np.float64).std(axis=0)
+    np.testing.assert_allclose(w[riros.MLP_PARAMS:riros.MLP_PARAMS + 6], mean, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(w[riros.MLP_PARAMS + 6:], std, rtol=1e-5)
+    xn = RM.normalise(x, mean, std)
+    L, g = RM.grad(p.astype(np.float64), xn, y)
+    z = np.zeros(RM.N_PARAMS)
+    p1, _, _ = RM.adam_step(p.astype(np.float64), g, z, z, 1, lr=1e-3)
+    # the first step moves each parameter by lr * g / (|g| + eps): compare the
+    # moves where the gradient is well above float32 rounding; elsewhere the
+    # move is bounded by lr
+    move, ref_move = w[:riros.MLP_PARAMS] - p, p1 - p
+    big = np.abs(g) > 1e-5
+    assert big.sum() > 1000
+    np.testing.assert_allclose(move[big], ref_move[big], atol=2e-6)
+    assert np.all(np.abs(move) <= 1e-3 * (1 + 1e-5))
+    assert abs(losses[0] - L) <= 1e-5 * L
+
+
+def test_inference_matches_reference():
+    p = W.mlp_init_weights(47)
+    mean = np.array([0.5, 0.2, 1, 3, 0.4, 0.5], dtype=np.float32)
+    std = np.ones(6, dtype=np.float32)
+    w = _weights_with_norm(p, mean, std)
+    x, _ = _batch(9, 5000)
+    got = riros.mlp_predict(w, x)
+    ref, _ = RM.forward(p.astype(np.float64), RM.normalise(x, mean, std))
+    np.testing.assert_allclose(got, ref, rtol=1e-4, atol=1e-4)
+
+
+def test_training_follows_reference_curve():
+    x, _ = _batch(13, 2048)
+    y = (2.0 * x[:, 0] - x[:, 3] + 0.5 * x[:, 5] * x[:, 5]).astype(np.float32)
+    p = W.mlp_init_weights(53)
+    w, losses = riros.mlp_train(x, y, p, epochs=5, batch=256, lr=2e-3)
+    mean, std = x.astype(np.float64).mean(axis=0), x.astype(np.float64).std(axis=0)
+    _, ref_losses = RM.train(p.astype(np.float64), RM.normalise(x, mean, std), y.astype(np.float64),
+                             epochs=5, batch=256, lr=2e-3)
+    assert losses.size == ref_losses.size
+    np.testing.assert_allclose(losses, ref_losses, rtol=2e-2)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_predictor_orders_work_and_never_changes_results(small):
+    """Train on other seeded designs, predict, and run two-dimensional mode with
+    and without the predicted order; detect cycles and events are identical."""
+    runs = []
+    for k in range(3):
+        wk = W.medium(seed=3000 + k, F=3000, T=400, n_nodes=4000)
+        dk = riros.Design(wk.design)
+        runs.append((dk, riros.Golden(dk, wk.stimulus, wk.T), wk.faults))
+    x, y = predictor.samples_from_runs(runs)
+    w, losses = predictor.train(x, y, epochs=20, batch=1024)
+    assert losses[-1] < losses[0]
+    d = riros.Design(small.design)
+    g = riros.Golden(d, small.stimulus, small.T)
+    pred = riros.mlp_predict(w, riros.features(d, g, small.faults))
+    base = riros.fault_sim(d, g, small.faults, mode=riros.MODE_TWO_D)
+    true_load = np.log2(1 + base[1].astype(np.float64))
+    err = predictor.load_error(pred, true_load)
+    print(f"[predictor] spearman={err['spearman']:.3f} mean|dlog2|={err['mean_abs_log2']:.3f}")
+    assert err["spearman"] > 0.3
+    for theta in (float("inf"), float(np.quantile(pred, 0.99))):
+        got = riros.fault_sim(d, g, small.faults, mode=riros.MODE_TWO_D, priority=pred, theta=theta,
+                              monitor_rate=2.0)
+        np.testing.assert_array_equal(got[0], base[0])
+        np.testing.assert_array_equal(got[1], base[1])
