@@ -131,8 +131,9 @@ typedef struct {
                               changes the schedule, never a result */
     float theta;           /* TWO_D: priority above which a fault starts on the
                               structural (heavy) path; +inf = all light */
-    int32_t light_cap;     /* TWO_D: per-lane divergent-node capacity (0 = default);
-                              a lane that overflows is moved to the heavy path */
+    int32_t light_cap;     /* TWO_D: per-lane divergent-node capacity, 4, 8 or 16
+                              (0 = 8); a lane that overflows hands its fault to
+                              the structural path */
     int32_t chunk;         /* reserved, must be 0 */
     float monitor_rate;    /* TWO_D: a light fault averaging more than this many
                               events per cycle after its first 8 cycles moves to
@@ -211,6 +212,37 @@ int riros_mlp_predict(const float* weights, const float* feats, uint32_t F, floa
  * loss float32[1].  The same kernels as training; for checking them. */
 int riros_mlp_grad(const float* weights, const float* feats, const float* y, uint32_t B, float* grad,
                    float* loss, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched campaigns: many designs, each with its own golden trace and fault  */
+/* list, simulated by one persistent two-dimensional launch over a single     */
+/* work queue of all their faults, captured once as a HIP graph and replayed. */
+/* ------------------------------------------------------------------------ */
+
+typedef struct riros_batch_s* riros_batch;
+
+/* Build a campaign of n designs (all loaded on the current device; goldens[i]
+ * belongs to designs[i]).  faults[i] is a host array of F[i] faults of design
+ * i; priority (may be NULL, and entries may be NULL for zero priority) gives
+ * per-fault predicted loads; the whole campaign is ordered by them, and
+ * faults above opts->theta start on the structural path.  opts->mode must be
+ * RIROS_MODE_TWO_D and opts->io_on_device 0; drop, waves_per_cu, light_cap
+ * and monitor_rate apply.  Inputs are uploaded and the run is captured as a
+ * graph.  Errors: RIROS_EINVAL (n == 0 or > 65536, mismatched goldens, invalid
+ * faults or options), RIROS_ENOMEM, RIROS_EDEVICE. */
+int riros_batch_create(uint32_t n, const riros_design* designs, const riros_golden* goldens,
+                       const riros_fault* const* faults, const uint32_t* F, const float* const* priority,
+                       const riros_sim_opts* opts, riros_batch* out);
+
+/* Run the whole campaign: one graph launch on `stream` (asynchronous).
+ * riros_last_kernel_ms then reports its duration. */
+int riros_batch_launch(riros_batch b, void* stream);
+
+/* Results of design i after the last launch (waits for it): detect[F[i]],
+ * events[F[i]] (may be NULL), coverage (may be NULL); host arrays. */
+int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, riros_coverage* cov);
+
+void riros_batch_free(riros_batch b);
 
 /* Number of nodes, levels and registers of a loaded design. */
 int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels, uint32_t* num_regs);

@@ -51,10 +51,14 @@ struct __attribute__((aligned(16))) Slot {
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s);
 
 struct PlainWorkspace {
-    Slot* slots;          // [blocks][N]
-    uint64_t* regs;       // [blocks][2][R]
-    uint64_t stamp_base;  // stamps above this value are unused in every block's slots
+    Slot* slots;              // [blocks][N]
+    uint64_t* regs;           // [blocks][2][R]
+    uint64_t* stamp_dev;      // device-resident: stamps above it are unused in every block's slots
 };
+
+// Advance the device-resident stamp base (the last launch of every run, so a
+// replayed graph never reuses a stamp).
+hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s);
 
 // Bytes of dynamic LDS the plain kernel needs for a design.
 size_t plain_lds_bytes(const DevDesign& d);

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
     uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * d.R;
-    uint64_t stamp0 = ws.stamp_base;
+    uint64_t stamp0 = *ws.stamp_dev;
     for (uint32_t fi = blockIdx.x; fi < F; fi += gridDim.x) {
         uint32_t det;
         uint64_t ev;
@@ -130,6 +130,17 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
             if (events_out) events_out[fi] = ev;
         }
     }
+}
+
+__global__ void k_advance_stamp(uint64_t* stamp_dev, uint64_t by)
+{
+    if (threadIdx.x == 0) *stamp_dev += by;
+}
+
+hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_stamp, dim3(1), dim3(64), 0, s, stamp_dev, by);
+    return hipGetLastError();
 }
 
 hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* G, uint32_t T,

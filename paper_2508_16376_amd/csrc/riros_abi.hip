@@ -14,6 +14,7 @@
 #include "mlp.hpp"
 #include "riros.h"
 #include "twod.hpp"
+#include "wave_fault.hpp"
 
 namespace {
 
@@ -89,7 +90,7 @@ struct riros_design_s {
     size_t ws_slots_cap = 0;
     uint64_t* ws_regs = nullptr;
     size_t ws_regs_cap = 0;
-    uint64_t stamp_next = 0;
+    uint64_t* stamp_dev = nullptr;   // slot stamps above this are unused (advanced on the device by every run)
     // two-dimensional kernel workspace
     riros::TwoDWorkspace twod{};
     // staging for host-side inputs and outputs
@@ -123,6 +124,7 @@ static void free_design_mem(riros_design d)
     d->owned.clear();
     if (d->ws_slots) (void)hipFree(d->ws_slots);
     if (d->ws_regs) (void)hipFree(d->ws_regs);
+    if (d->stamp_dev) (void)hipFree(d->stamp_dev);
     if (d->stage) (void)hipFree(d->stage);
     if (d->d_cov) (void)hipFree(d->d_cov);
     if (d->d_bad) (void)hipFree(d->d_bad);
@@ -179,6 +181,8 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
                               p_rec, p_fopk, p_bp, im.N, im.L, im.R, im.npi, im.bp_rows};
     e = hipMalloc((void**)&d->d_cov, sizeof(riros_coverage));
     if (e == hipSuccess) e = hipMalloc((void**)&d->d_bad, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&d->stamp_dev, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(d->stamp_dev, 0, sizeof(uint64_t));
     if (e != hipSuccess) {
         free_design_mem(d);
         delete d;
@@ -296,7 +300,6 @@ static int ensure_plain_ws(riros_design d, uint32_t blocks, hipStream_t s)
         HIP_TRY(hipMalloc((void**)&d->ws_slots, nslots * sizeof(riros::Slot)), "workspace allocation");
         HIP_TRY(hipMemsetAsync(d->ws_slots, 0, nslots * sizeof(riros::Slot), s), "workspace clear");
         d->ws_slots_cap = nslots;
-        d->stamp_next = 0;
     }
     if (d->ws_regs_cap < nregs) {
         HIP_TRY(hipStreamSynchronize(s), "workspace sync");
@@ -317,8 +320,10 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
     if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
         return set_err(RIROS_EINVAL, "unknown mode");
-    if (opts->waves_per_cu < 0 || opts->light_cap < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f))
-        return set_err(RIROS_EINVAL, "invalid option (negative count, nonzero chunk or bad monitor_rate)");
+    if (opts->waves_per_cu < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f) ||
+        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
+        return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, chunk != 0, bad monitor_rate, or "
+                                     "light_cap not 0, 4, 8 or 16)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -386,13 +391,13 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         int rc = ensure_plain_ws(d, blocks, s);
         if (rc) return rc;
         const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
-        riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_next};
-        d->stamp_next += per_block * T + 1;
+        riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_dev};
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
         HIP_TRY(riros::launch_fault_plain(d->dev, g->G, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
                                           d_events, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
+        HIP_TRY(riros::launch_advance_stamp(d->stamp_dev, per_block * T + 1, s), "stamp advance");
     } else {
         const size_t lds = riros::plain_lds_bytes(d->dev);
         if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");
@@ -402,8 +407,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         const uint32_t heavy_blocks = (uint32_t)d->num_cu * (uint32_t)wpc;
         int rc = ensure_plain_ws(d, heavy_blocks, s);
         if (rc) return rc;
-        riros::PlainWorkspace hws{d->ws_slots, d->ws_regs, d->stamp_next};
-        d->stamp_next += 2 * ((uint64_t)F * T + 1);
+        riros::PlainWorkspace hws{d->ws_slots, d->ws_regs, d->stamp_dev};
         riros::TwoDParams p;
         p.monitor_rate = opts->monitor_rate;
         p.theta = opts->theta;
@@ -569,6 +573,231 @@ int riros_mlp_grad(const float* weights, const float* feats, const float* y, uin
     HIP_TRY(hipMemcpyAsync(loss, dl.p, sizeof(float), hipMemcpyDeviceToHost, s), "download");
     HIP_TRY(hipStreamSynchronize(s), "sync");
     return RIROS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched campaigns
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct riros_batch_s {
+    int device = 0;
+    uint32_t n = 0, F = 0;
+    std::vector<uint32_t> off;        // host copy of the fault offsets
+    riros::BatchPlan plan{};
+    riros::TwoDWorkspace tw{};
+    std::vector<void*> owned;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last_stream = nullptr;
+};
+
+static void free_batch(riros_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (void* p : b->owned) (void)hipFree(p);
+    riros::twod_free(b->tw);
+}
+
+template <class T>
+static hipError_t batch_alloc(riros_batch b, T** p, size_t n)
+{
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) b->owned.push_back((void*)*p);
+    return e;
+}
+
+extern "C" {
+
+int riros_batch_create(uint32_t n, const riros_design* designs, const riros_golden* goldens,
+                       const riros_fault* const* faults, const uint32_t* F, const float* const* priority,
+                       const riros_sim_opts* opts, riros_batch* out)
+{
+    if (!designs || !goldens || !faults || !F || !opts || !out) return set_err(RIROS_EINVAL, "NULL argument");
+    if (n == 0 || n > 65536) return set_err(RIROS_EINVAL, "n must be in 1..65536");
+    if (opts->mode != RIROS_MODE_TWO_D || opts->io_on_device)
+        return set_err(RIROS_EINVAL, "campaigns run in RIROS_MODE_TWO_D with host-side inputs");
+    if (opts->waves_per_cu < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f) ||
+        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
+        return set_err(RIROS_EINVAL, "invalid option");
+    const int dev = designs[0] ? designs[0]->device : 0;
+    uint64_t total = 0;
+    uint32_t Nmax = 0, Lmax = 0, Rmax = 0, Tmax = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!designs[i] || !goldens[i] || goldens[i]->d != designs[i])
+            return set_err(RIROS_EINVAL, "design " + std::to_string(i) + ": missing or mismatched golden trace");
+        if (designs[i]->device != dev) return set_err(RIROS_EINVAL, "designs on different devices");
+        if (F[i] > 0 && !faults[i]) return set_err(RIROS_EINVAL, "faults[" + std::to_string(i) + "] is NULL");
+        const riros::Image& im = designs[i]->img;
+        for (uint32_t j = 0; j < F[i]; ++j) {
+            const riros_fault& f = faults[i][j];
+            if (f.site >= im.N || f.stuck > 1 || f.bit >= im.desc[im.u2i[f.site]].width)
+                return set_err(RIROS_EINVAL, "design " + std::to_string(i) + " fault " + std::to_string(j) + " invalid");
+        }
+        total += F[i];
+        Nmax = std::max(Nmax, im.N);
+        Lmax = std::max(Lmax, im.L);
+        Rmax = std::max(Rmax, im.R);
+        Tmax = std::max(Tmax, goldens[i]->T);
+    }
+    if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
+    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax) * sizeof(uint32_t);
+    if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "largest design too large for the structural path's LDS bitmap");
+    DeviceGuard guard(dev);
+    riros_batch b = new (std::nothrow) riros_batch_s();
+    if (!b) return set_err(RIROS_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->n = n;
+    b->F = (uint32_t)total;
+    auto fail = [&](int code, const std::string& m) {
+        free_batch(b);
+        delete b;
+        return set_err(code, m);
+    };
+    // Host staging: tables, concatenated faults, design ids, offsets, priorities.
+    std::vector<riros::DevDesign> td(n);
+    std::vector<riros::GoldenView> tg(n);
+    std::vector<riros_fault> fl(b->F);
+    std::vector<uint16_t> did(b->F);
+    std::vector<float> pr;
+    const bool any_prio = priority != nullptr;
+    if (any_prio) pr.assign(b->F, 0.f);
+    b->off.assign(n + 1, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        td[i] = designs[i]->dev;
+        tg[i] = goldens[i]->view();
+        const uint32_t o = b->off[i];
+        if (F[i]) std::memcpy(&fl[o], faults[i], (size_t)F[i] * sizeof(riros_fault));
+        for (uint32_t j = 0; j < F[i]; ++j) did[o + j] = (uint16_t)i;
+        if (any_prio && priority[i]) std::memcpy(&pr[o], priority[i], (size_t)F[i] * sizeof(float));
+        b->off[i + 1] = o + F[i];
+    }
+    riros::BatchPlan& p = b->plan;
+    riros::DevDesign* d_td = nullptr;
+    riros::GoldenView* d_tg = nullptr;
+    riros_fault* d_fl = nullptr;
+    uint16_t* d_did = nullptr;
+    uint32_t* d_off = nullptr;
+    float* d_pr = nullptr;
+    uint32_t* d_det = nullptr;
+    uint64_t* d_ev = nullptr;
+    riros_coverage* d_cov = nullptr;
+    riros::Slot* d_slots = nullptr;
+    uint64_t* d_regs = nullptr;
+    uint64_t* d_stamp = nullptr;
+    int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 12;
+    wpc = std::min(std::min(wpc, (int)std::max<size_t>(1, (160 * 1024) / lds)), 32);
+    const uint32_t blocks = (uint32_t)designs[0]->num_cu * (uint32_t)wpc;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    A(batch_alloc(b, &d_td, n));
+    A(batch_alloc(b, &d_tg, n));
+    A(batch_alloc(b, &d_fl, b->F));
+    A(batch_alloc(b, &d_did, b->F));
+    A(batch_alloc(b, &d_off, n + 1));
+    if (any_prio) A(batch_alloc(b, &d_pr, b->F));
+    A(batch_alloc(b, &d_det, b->F));
+    A(batch_alloc(b, &d_ev, b->F));
+    A(batch_alloc(b, &d_cov, n));
+    A(batch_alloc(b, &d_slots, (size_t)blocks * Nmax));
+    A(batch_alloc(b, &d_regs, (size_t)blocks * 2 * std::max(Rmax, 1u)));
+    A(batch_alloc(b, &d_stamp, 1));
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? RIROS_ENOMEM : RIROS_EDEVICE, "campaign allocation");
+    A(hipMemcpy(d_td, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice));
+    A(hipMemcpy(d_tg, tg.data(), n * sizeof(riros::GoldenView), hipMemcpyHostToDevice));
+    if (b->F) {
+        A(hipMemcpy(d_fl, fl.data(), fl.size() * sizeof(riros_fault), hipMemcpyHostToDevice));
+        A(hipMemcpy(d_did, did.data(), did.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        if (any_prio) A(hipMemcpy(d_pr, pr.data(), pr.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    A(hipMemcpy(d_off, b->off.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice));
+    A(hipMemset(d_slots, 0, (size_t)blocks * Nmax * sizeof(riros::Slot)));
+    A(hipMemset(d_stamp, 0, sizeof(uint64_t)));
+    A(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign upload: ") + hipGetErrorString(e));
+    p.n = n;
+    p.F = b->F;
+    p.td = d_td;
+    p.tg = d_tg;
+    p.did = d_did;
+    p.off = d_off;
+    p.Nmax = Nmax;
+    p.Lmax = Lmax;
+    p.Rmax = Rmax;
+    p.faults = d_fl;
+    p.drop = opts->drop ? 1 : 0;
+    p.light_cap = opts->light_cap ? opts->light_cap : 8;
+    p.rate_num = opts->monitor_rate > 0.f ? (uint32_t)std::min(4.0e9f, opts->monitor_rate * 4.f + 0.5f) : 0u;
+    p.blocks = blocks;
+    p.span = (uint64_t)b->F * Tmax + 1;
+    p.ws = riros::PlainWorkspace{d_slots, d_regs, d_stamp};
+    p.detect = d_det;
+    p.events = d_ev;
+    p.cov = d_cov;
+    std::string err;
+    int rc = riros::order_batch(b->tw, d_pr, b->F, opts->theta, &p.order, b->cap_stream, err);
+    if (rc) return fail(rc, err);
+    e = hipStreamSynchronize(b->cap_stream);
+    if (e == hipSuccess) e = riros::prepare_twod_batch(p);
+    if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign preparation: ") + hipGetErrorString(e));
+    // Capture the run as a graph.
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = riros::launch_twod_batch(p, b->tw, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign graph capture: ") + hipGetErrorString(e));
+    *out = b;
+    return RIROS_OK;
+}
+
+int riros_batch_launch(riros_batch b, void* stream)
+{
+    if (!b) return set_err(RIROS_EINVAL, "NULL campaign");
+    DeviceGuard guard(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (!g_ev0) {
+        HIP_TRY(hipEventCreate(&g_ev0), "event create");
+        HIP_TRY(hipEventCreate(&g_ev1), "event create");
+    }
+    HIP_TRY(hipEventRecord(g_ev0, s), "event record");
+    HIP_TRY(hipGraphLaunch(b->exec, s), "campaign graph launch");
+    HIP_TRY(hipEventRecord(g_ev1, s), "event record");
+    g_ev_valid = true;
+    b->last_stream = s;
+    return RIROS_OK;
+}
+
+int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, riros_coverage* cov)
+{
+    if (!b) return set_err(RIROS_EINVAL, "NULL campaign");
+    if (i >= b->n) return set_err(RIROS_EINVAL, "design index out of range");
+    const uint32_t o = b->off[i], cnt = b->off[i + 1] - b->off[i];
+    if (cnt > 0 && !detect) return set_err(RIROS_EINVAL, "detect is NULL");
+    DeviceGuard guard(b->device);
+    HIP_TRY(hipStreamSynchronize(b->last_stream), "campaign sync");
+    if (cnt) {
+        HIP_TRY(hipMemcpy(detect, b->plan.detect + o, (size_t)cnt * 4, hipMemcpyDeviceToHost), "detect download");
+        if (events)
+            HIP_TRY(hipMemcpy(events, b->plan.events + o, (size_t)cnt * 8, hipMemcpyDeviceToHost), "events download");
+    }
+    if (cov) HIP_TRY(hipMemcpy(cov, b->plan.cov + i, sizeof(riros_coverage), hipMemcpyDeviceToHost), "coverage download");
+    return RIROS_OK;
+}
+
+void riros_batch_free(riros_batch b)
+{
+    if (!b) return;
+    DeviceGuard guard(b->device);
+    (void)hipDeviceSynchronize();
+    free_batch(b);
+    delete b;
 }
 
 }  // extern "C"

@@ -109,6 +109,33 @@ __device__ __forceinline__ uint32_t pick4(uint32_t k, uint32_t a, uint32_t b, ui
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
 }
 
+// Per-lane view of a fault's design: everything the light path reads.
+struct LaneDesign {
+    const uint32_t* u2i;
+    const NodeRec* rec;
+    const uint32_t* fo;
+    const uint32_t* rfo;
+    const uint32_t* bp_off;
+    const uint64_t* Gn;
+    const uint64_t* Bp;
+    uint32_t T, TW;
+};
+
+__device__ __forceinline__ LaneDesign lane_design(const DevDesign& d, const GoldenView& g)
+{
+    return LaneDesign{d.u2i, d.rec, d.fo, d.rfo, d.bp_off, g.Gn, g.Bp, g.T, g.TW};
+}
+
+// Where a fault's design comes from: the launch's one design, or (batched
+// campaigns) a device table indexed by the fault's design id.
+struct DesignSrc {
+    DevDesign d;
+    GoldenView g;
+    const DevDesign* td;
+    const GoldenView* tg;
+    const uint16_t* did;
+};
+
 // Phase 2: light faults one per lane.  A lane with no divergent register
 // skips straight to the next cycle in which its site is excited (the site's
 // bit differs from the stuck value), reading 64 cycles of that bit with one
@@ -116,8 +143,8 @@ __device__ __forceinline__ uint32_t pick4(uint32_t k, uint32_t a, uint32_t b, ui
 // faulty = golden ^ (1 << bit).  Otherwise the lane evaluates its pending
 // nodes in increasing id order (a topological order) from the node-major
 // golden values of the operands xor their divergence deltas.
-template <int C>
-__device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riros_fault* __restrict__ faults,
+template <int C, bool BATCH>
+__device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict__ faults,
                             uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
                             uint64_t* __restrict__ events_out, uint32_t lanes, uint32_t rate_num)
@@ -125,9 +152,8 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
     constexpr int CR = C / 2;
     constexpr uint32_t kPre = 4;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t T = gw.T, TW = gw.TW;
-    const uint64_t* __restrict__ Gn = gw.Gn;
-    const uint64_t* __restrict__ Bp = gw.Bp;
+    // One design: uniform for the whole wave.  Batched: per lane, per fault.
+    LaneDesign d = lane_design(src.d, src.g);
 
     uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, t = 0, det = RIROS_UNDETECTED;
     uint64_t ev = 0;
@@ -160,12 +186,16 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
                 const uint32_t idx = base + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
                 if (idx < nlight) {
                     fi = lorder ? lorder[idx] : idx;
+                    if (BATCH) {
+                        const uint32_t k = src.did[fi];
+                        d = lane_design(src.td[k], src.tg[k]);
+                    }
                     const riros_fault f = faults[fi];
                     site = d.u2i[f.site];
                     fbit = f.bit;
                     fval = f.stuck;
                     srec = d.rec[site];
-                    bprow = (size_t)(d.bp_off[site] + fbit) * TW;
+                    bprow = (size_t)(d.bp_off[site] + fbit) * d.TW;
                     const uint32_t nf = srec.fo1 - srec.fo0;
                     sf0 = nf > 0 ? d.fo[srec.fo0] : 0;
                     sf1 = nf > 1 ? d.fo[srec.fo0 + 1] : 0;
@@ -204,10 +234,11 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
             if (rcur.n == 0) {
                 // Skip to the next cycle in which the site is excited.
                 bool found = false;
+                const uint32_t T = d.T;
                 while (t < T) {
                     const uint32_t wb = t >> 6;
                     if (wb != ewb) {
-                        uint64_t w = Bp[bprow + wb];
+                        uint64_t w = d.Bp[bprow + wb];
                         if (fval) w = ~w;
                         const uint32_t valid = T - (wb << 6);
                         if (valid < 64) w &= (1ull << valid) - 1ull;
@@ -243,7 +274,8 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
             // Evaluate the lowest pending node (users always have larger ids).
             const uint32_t n = pend.pop_min();
             const NodeRec r = d.rec[n];
-            const uint64_t gv = Gn[(size_t)n * T + t];
+            const uint32_t T = d.T;
+            const uint64_t gv = d.Gn[(size_t)n * T + t];
             const uint32_t nf = r.fo1 - r.fo0;
             const uint32_t p0 = nf > 0 ? d.fo[r.fo0] : 0;
             const uint32_t p1 = nf > 1 ? d.fo[r.fo0 + 1] : 0;
@@ -259,7 +291,7 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
                 uint64_t xs[3] = {0, 0, 0};
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
-                    if (k < ar) xs[k] = Gn[(size_t)ins[k] * T + t];
+                    if (k < ar) xs[k] = d.Gn[(size_t)ins[k] * T + t];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
                     if (k < ar) xs[k] ^= div.find(ins[k], din);
@@ -289,7 +321,7 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
                 rcur = rnxt;
                 rnxt.n = 0;
                 in_cycle = false;
-                done = t >= T;
+                done = t >= d.T;
             }
             if (done) {
                 detect_out[fi] = det;
@@ -300,20 +332,48 @@ __device__ void light_phase(const DevDesign& d, const GoldenView& gw, const riro
     }
 }
 
-template <int C>
-__global__ __launch_bounds__(64) void k_twod_a(DevDesign d, GoldenView gw, const riros_fault* __restrict__ faults,
+// Structural path for one fault, on the fault's design.
+template <bool BATCH>
+__device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, const riros_fault* __restrict__ faults,
+                                          int drop, const WaveLds& s, Slot* slots, uint64_t* regs,
+                                          uint64_t& stamp0, uint32_t* __restrict__ detect_out,
+                                          uint64_t* __restrict__ events_out)
+{
+    uint32_t det;
+    uint64_t ev;
+    if (BATCH) {
+        const uint32_t k = src.did[fi];
+        const DevDesign dd = src.td[k];
+        const GoldenView gg = src.tg[k];
+        wave_sim_fault(dd, gg.G, gg.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+    } else {
+        wave_sim_fault(src.d, src.g.G, src.g.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+    }
+    if (threadIdx.x == 0) {
+        detect_out[fi] = det;
+        if (events_out) events_out[fi] = ev;
+    }
+}
+
+// Shapes of the largest design of a launch (LDS and workspace are sized by it).
+struct MaxShape {
+    uint32_t N, L, R;
+};
+
+template <int C, bool BATCH>
+__global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
                                                uint32_t F, const uint32_t* __restrict__ order, TwoDCounters* ctr,
                                                uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-                                               uint32_t rate_num, uint32_t* __restrict__ detect_out,
-                                               uint64_t* __restrict__ events_out)
+                                               uint32_t rate_num,
+                                               uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
-    wave_lds_clear(s, d.N, d.L, d.R);
+    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+    wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
-    Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
-    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * d.R;
-    uint64_t stamp0 = ws.stamp_base;
+    Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
+    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
+    uint64_t stamp0 = *ws.stamp_dev;
     const uint32_t nh = ctr->n_heavy;
     // Phase 1: heavy faults placed up front.
     for (;;) {
@@ -321,50 +381,39 @@ __global__ __launch_bounds__(64) void k_twod_a(DevDesign d, GoldenView gw, const
         if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
         idx = __shfl(idx, 0, 64);
         if (idx >= nh) break;
-        const uint32_t fi = order ? order[idx] : idx;
-        uint32_t det;
-        uint64_t ev;
-        wave_sim_fault(d, gw.G, gw.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
-        if (threadIdx.x == 0) {
-            detect_out[fi] = det;
-            if (events_out) events_out[fi] = ev;
-        }
+        heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
+                         events_out);
     }
     // Phase 2: light faults, one per lane; each wavefront takes at most its
     // share of lanes so that light faults spread over every wavefront.
     const uint32_t nlight = F - nh;
     const uint32_t lanes = min(64u, max(1u, (nlight + gridDim.x - 1) / gridDim.x));
-    light_phase<C>(d, gw, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out, events_out,
-                   lanes, rate_num);
+    light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
+                          events_out, lanes, rate_num);
 }
 
 // Launch B: the faults handed over in launch A (their list is complete).
-__global__ __launch_bounds__(64) void k_twod_b(DevDesign d, GoldenView gw, const riros_fault* __restrict__ faults,
+// Stamps continue above the largest range launch A can have used (span).
+template <bool BATCH>
+__global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
                                                TwoDCounters* ctr, const uint32_t* __restrict__ esc, int drop,
-                                               PlainWorkspace ws, uint32_t* __restrict__ detect_out,
+                                               PlainWorkspace ws, uint64_t span, uint32_t* __restrict__ detect_out,
                                                uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
-    wave_lds_clear(s, d.N, d.L, d.R);
+    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+    wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
-    Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
-    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * d.R;
-    uint64_t stamp0 = ws.stamp_base;
+    Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
+    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
+    uint64_t stamp0 = *ws.stamp_dev + span;
     const uint32_t n = ctr->esc_count;
     for (;;) {
         uint32_t idx = 0;
         if (threadIdx.x == 0) idx = atomicAdd(&ctr->esc_head, 1u);
         idx = __shfl(idx, 0, 64);
         if (idx >= n) break;
-        const uint32_t fi = esc[idx];
-        uint32_t det;
-        uint64_t ev;
-        wave_sim_fault(d, gw.G, gw.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
-        if (threadIdx.x == 0) {
-            detect_out[fi] = det;
-            if (events_out) events_out[fi] = ev;
-        }
+        heavy_one<BATCH>(src, esc[idx], faults, drop, s, slots, regs, stamp0, detect_out, events_out);
     }
 }
 
@@ -397,6 +446,55 @@ __global__ void k_zero_counters(TwoDCounters* ctr)
     if (threadIdx.x < sizeof(TwoDCounters) / 4) ((uint32_t*)ctr)[threadIdx.x] = 0;
 }
 
+// Reset the per-run counters, keeping the heavy-queue length fixed when the
+// campaign was ordered.
+__global__ void k_reset_run_counters(TwoDCounters* ctr)
+{
+    if (threadIdx.x == 0) {
+        ctr->light_head = 0;
+        ctr->esc_count = 0;
+        ctr->heavy_head = 0;
+        ctr->esc_head = 0;
+        ctr->error = 0;
+    }
+}
+
+// Coverage of each design of a campaign: workgroup k reduces faults
+// off[k]..off[k+1] with that design's cycle count.
+__global__ __launch_bounds__(256) void k_batch_coverage(const uint32_t* __restrict__ detect,
+                                                        const uint64_t* __restrict__ events,
+                                                        const uint32_t* __restrict__ off,
+                                                        const GoldenView* __restrict__ tg,
+                                                        riros_coverage* __restrict__ cov)
+{
+    __shared__ unsigned long long red[3][4];
+    const uint32_t k = blockIdx.x;
+    const uint32_t T = tg[k].T;
+    unsigned long long det = 0, fc = 0, ev = 0;
+    for (uint32_t i = off[k] + threadIdx.x; i < off[k + 1]; i += blockDim.x) {
+        const uint32_t dc = detect[i];
+        det += dc != RIROS_UNDETECTED;
+        fc += dc != RIROS_UNDETECTED ? (unsigned long long)dc + 1 : T;
+        ev += events[i];
+    }
+    det = wave_sum_u64(det);
+    fc = wave_sum_u64(fc);
+    ev = wave_sum_u64(ev);
+    const uint32_t w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = det;
+        red[1][w] = fc;
+        red[2][w] = ev;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cov[k].detected = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        cov[k].total = off[k + 1] - off[k];
+        cov[k].fault_cycles = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        cov[k].events = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    }
+}
+
 struct TwoDLayout {
     size_t ctr, esc, order, idx, keys_out, temp, total;
     size_t temp_bytes;
@@ -418,40 +516,70 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     return l;
 }
 
-template <int C>
-static hipError_t launch_twod_c(const DevDesign& d, const GoldenView& gw, const riros_fault* faults, uint32_t F,
+template <int C, bool BATCH>
+static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
                                 const uint32_t* order, TwoDCounters* ctr, uint32_t* esc, int drop,
-                                const PlainWorkspace& ws, uint32_t blocks, uint32_t rate_num, uint32_t* detect,
-                                uint64_t* events, hipStream_t s)
+                                const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
+                                uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
-    const size_t lds = wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
-    hipError_t e = hipFuncSetAttribute((const void*)k_twod_a<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const size_t lds = wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
+    hipError_t e = hipFuncSetAttribute((const void*)k_twod_a<C, BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_twod_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_twod_a<C>, dim3(blocks), dim3(64), lds, s, d, gw, faults, F, order, ctr, esc, drop, ws,
-                       rate_num, detect, events);
-    PlainWorkspace wsb = ws;
-    wsb.stamp_base = ws.stamp_base + (uint64_t)F * gw.T + 1;
-    hipLaunchKernelGGL(k_twod_b, dim3(blocks), dim3(64), lds, s, d, gw, faults, ctr, esc, drop, wsb, detect,
-                       events);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_twod_a<C, BATCH>), dim3(blocks), dim3(64), lds, s, src, mx, faults, F, order, ctr, esc,
+                       drop, ws, rate_num, detect, events);
+    hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(blocks), dim3(64), lds, s, src, mx, faults, ctr, esc, drop, ws, span,
+                       detect, events);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_advance_stamp(ws.stamp_dev, 2 * span, s);
 }
 
-int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const riros_fault* faults,
-             const float* priority, uint32_t F, int drop, const TwoDParams& p, PlainWorkspace heavy_ws,
-             uint32_t blocks, uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
-             std::string& err)
+template <bool BATCH>
+static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
+                                  uint32_t F, const uint32_t* order, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                  const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
+                                  uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
+{
+    switch (cap) {
+    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    }
+}
+
+// Ordering by priority (descending) and the heavy prefix count; outside any
+// graph (the sort may use library-internal memory operations).
+static int order_by_priority(TwoDWorkspace& ws, const TwoDLayout& lay, const float* priority, uint32_t F,
+                             float theta, TwoDCounters* ctr, hipStream_t s, std::string& err)
+{
+    char* base = (char*)ws.mem;
+    uint32_t* idx = (uint32_t*)(base + lay.idx);
+    float* keys_out = (float*)(base + lay.keys_out);
+    uint32_t* order = (uint32_t*)(base + lay.order);
+    hipLaunchKernelGGL(k_iota, dim3((F + 255) / 256), dim3(256), 0, s, idx, F);
+    size_t tb = lay.temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, priority, keys_out, idx, order,
+                                                               (int)F, 0, 32, s);
+    if (e != hipSuccess) { err = "priority sort failed"; return RIROS_EDEVICE; }
+    if (!(theta > 3.0e38f))
+        hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, theta, ctr);
+    return RIROS_OK;
+}
+
+static int ensure_twod_ws(TwoDWorkspace& ws, uint32_t F, bool with_sort, TwoDLayout& lay, std::string& err,
+                          hipStream_t s)
 {
     size_t temp_bytes = 0;
-    if (priority) {
+    if (with_sort) {
         hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, temp_bytes, (const float*)nullptr,
                                                                    (float*)nullptr, (const uint32_t*)nullptr,
                                                                    (uint32_t*)nullptr, (int)F, 0, 32, s);
         if (e != hipSuccess) { err = "sort size query failed"; return RIROS_EDEVICE; }
     }
-    const TwoDLayout lay = layout_for(F, temp_bytes);
+    lay = layout_for(F, temp_bytes);
     if (ws.bytes < lay.total) {
         if (ws.mem) (void)hipFree(ws.mem);
         ws.mem = nullptr;
@@ -459,38 +587,95 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
         if (hipMalloc(&ws.mem, lay.total) != hipSuccess) { err = "two-dimensional workspace allocation"; return RIROS_ENOMEM; }
         ws.bytes = lay.total;
     }
+    ws.ctr = ws.mem;
+    return RIROS_OK;
+}
+
+int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const riros_fault* faults,
+             const float* priority, uint32_t F, int drop, const TwoDParams& p, PlainWorkspace heavy_ws,
+             uint32_t blocks, uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
+             std::string& err)
+{
+    TwoDLayout lay;
+    int rc = ensure_twod_ws(ws, F, priority != nullptr, lay, err, s);
+    if (rc) return rc;
     char* base = (char*)ws.mem;
     TwoDCounters* ctr = (TwoDCounters*)(base + lay.ctr);
     uint32_t* esc = (uint32_t*)(base + lay.esc);
-    uint32_t* order = nullptr;
-    ws.ctr = ctr;
-
     if (hipEventRecord(ev0, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
+    const uint32_t* order = nullptr;
     if (priority) {
-        uint32_t* idx = (uint32_t*)(base + lay.idx);
-        float* keys_out = (float*)(base + lay.keys_out);
-        order = (uint32_t*)(base + lay.order);
-        hipLaunchKernelGGL(k_iota, dim3((F + 255) / 256), dim3(256), 0, s, idx, F);
-        size_t tb = lay.temp_bytes;
-        hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, priority, keys_out, idx,
-                                                                   order, (int)F, 0, 32, s);
-        if (e != hipSuccess) { err = "priority sort failed"; return RIROS_EDEVICE; }
-        if (!(p.theta > 3.0e38f))
-            hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, p.theta, ctr);
+        rc = order_by_priority(ws, lay, priority, F, p.theta, ctr, s, err);
+        if (rc) return rc;
+        order = (const uint32_t*)(base + lay.order);
     }
-    hipError_t e;
     const uint32_t rate_num = p.monitor_rate > 0.f ? (uint32_t)std::min(4.0e9f, p.monitor_rate * 4.f + 0.5f) : 0u;
-    switch (p.light_cap) {
-    case 4: e = launch_twod_c<4>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
-    case 16: e = launch_twod_c<16>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
-    case 0:
-    case 8: e = launch_twod_c<8>(d, gw, faults, F, order, ctr, esc, drop, heavy_ws, blocks, rate_num, detect, events, s); break;
-    default: err = "light_cap must be 4, 8 or 16"; return RIROS_EINVAL;
-    }
-    if (e != hipSuccess) { err = std::string("two-dimensional kernel: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
+    DesignSrc src{d, gw, nullptr, nullptr, nullptr};
+    const MaxShape mx{d.N, d.L, d.R};
+    const uint64_t span = (uint64_t)F * gw.T + 1;
+    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, ctr, esc, drop, heavy_ws, span,
+                                          blocks, rate_num, detect, events, s);
+    if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     return RIROS_OK;
+}
+
+hipError_t prepare_twod_batch(const BatchPlan& b)
+{
+    const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
+    hipError_t e = hipSuccess;
+    auto attr = [&](const void* f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    attr((const void*)k_twod_a<4, true>);
+    attr((const void*)k_twod_a<8, true>);
+    attr((const void*)k_twod_a<16, true>);
+    attr((const void*)k_twod_b<true>);
+    return e;
+}
+
+int order_batch(TwoDWorkspace& ws, const float* priority, uint32_t F, float theta, const uint32_t** order,
+                hipStream_t s, std::string& err)
+{
+    TwoDLayout lay;
+    int rc = ensure_twod_ws(ws, F, priority != nullptr, lay, err, s);
+    if (rc) return rc;
+    char* base = (char*)ws.mem;
+    TwoDCounters* ctr = (TwoDCounters*)(base + lay.ctr);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
+    *order = nullptr;
+    if (priority) {
+        rc = order_by_priority(ws, lay, priority, F, theta, ctr, s, err);
+        if (rc) return rc;
+        *order = (const uint32_t*)(base + lay.order);
+    }
+    return RIROS_OK;
+}
+
+hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t s)
+{
+    const TwoDLayout lay = layout_for(b.F, 0);
+    char* base = (char*)ws.mem;
+    TwoDCounters* ctr = (TwoDCounters*)(base + lay.ctr);
+    uint32_t* esc = (uint32_t*)(base + lay.esc);
+    hipLaunchKernelGGL(k_reset_run_counters, dim3(1), dim3(64), 0, s, ctr);
+    DesignSrc src{b.td_host0, b.tg_host0, b.td, b.tg, b.did};
+    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
+    const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
+    switch (b.light_cap) {
+    case 4: hipLaunchKernelGGL((k_twod_a<4, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
+    case 16: hipLaunchKernelGGL((k_twod_a<16, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
+    default: hipLaunchKernelGGL((k_twod_a<8, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
+    }
+    hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
+                       b.span, b.detect, b.events);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_advance_stamp(b.ws.stamp_dev, 2 * b.span, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_coverage, dim3(b.n), dim3(256), 0, s, b.detect, b.events, b.off, b.tg, b.cov);
+    return hipGetLastError();
 }
 
 void twod_free(TwoDWorkspace& ws)

@@ -28,7 +28,8 @@ MODE_TWO_D = 1
 
 EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros_free_golden",
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
-            "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad"]
+            "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad",
+            "riros_batch_create", "riros_batch_launch", "riros_batch_read", "riros_batch_free"]
 N_FEATURES = 6
 MLP_PARAMS = 4673
 MLP_WEIGHTS = MLP_PARAMS + 12
@@ -123,6 +124,14 @@ def lib():
         L.riros_mlp_predict.restype = I
         L.riros_mlp_grad.argtypes = [P, P, P, U, P, P, P]
         L.riros_mlp_grad.restype = I
+        L.riros_batch_create.argtypes = [U, P, P, P, P, P, ctypes.POINTER(SimOpts), ctypes.POINTER(P)]
+        L.riros_batch_create.restype = I
+        L.riros_batch_launch.argtypes = [P, P]
+        L.riros_batch_launch.restype = I
+        L.riros_batch_read.argtypes = [P, U, P, P, ctypes.POINTER(Coverage)]
+        L.riros_batch_read.restype = I
+        L.riros_batch_free.argtypes = [P]
+        L.riros_batch_free.restype = None
         _lib = L
     return _lib
 
@@ -296,3 +305,51 @@ def mlp_grad(weights: np.ndarray, feats: np.ndarray, y: np.ndarray):
     loss = np.empty(1, dtype=np.float32)
     _check(lib().riros_mlp_grad(_ptr(w), _ptr(x), _ptr(yy), x.shape[0], _ptr(g), _ptr(loss), None))
     return g, float(loss[0])
+
+
+class Batch:
+    """riros_batch_create handle: a campaign of designs run as one graph launch."""
+
+    def __init__(self, designs, goldens, fault_lists, priorities=None, *, drop=True, waves_per_cu=0,
+                 theta=math.inf, light_cap=0, monitor_rate=0.0):
+        n = len(designs)
+        fls = [np.ascontiguousarray(f) for f in fault_lists]
+        self.F = [int(f.size) for f in fls]
+        dh = (ctypes.c_void_p * n)(*[d.handle.value for d in designs])
+        gh = (ctypes.c_void_p * n)(*[g.handle.value for g in goldens])
+        fp = (ctypes.c_void_p * n)(*[f.ctypes.data for f in fls])
+        Fa = np.asarray(self.F, dtype=np.uint32)
+        pp = None
+        keep = []
+        if priorities is not None:
+            prs = [None if p is None else np.ascontiguousarray(p, dtype=np.float32) for p in priorities]
+            keep = prs
+            pp = (ctypes.c_void_p * n)(*[0 if p is None else p.ctypes.data for p in prs])
+        opts = make_opts(MODE_TWO_D, drop, False, waves_per_cu, None, theta, light_cap, 0, monitor_rate, None)
+        h = ctypes.c_void_p()
+        _check(lib().riros_batch_create(n, dh, gh, fp, _ptr(Fa), pp, ctypes.byref(opts), ctypes.byref(h)))
+        del keep
+        self.handle = h
+        self.n = n
+        self.designs, self.goldens = designs, goldens   # keep the handles alive
+
+    def launch(self, stream=None):
+        _check(lib().riros_batch_launch(self.handle, _stream_ptr(stream)))
+
+    def read(self, i):
+        det = np.empty(self.F[i], dtype=np.uint32)
+        ev = np.empty(self.F[i], dtype=np.uint64)
+        cov = Coverage()
+        _check(lib().riros_batch_read(self.handle, i, _ptr(det), _ptr(ev), ctypes.byref(cov)))
+        return det, ev, cov.as_dict()
+
+    def close(self):
+        if self.handle:
+            lib().riros_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

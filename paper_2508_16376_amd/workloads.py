@@ -381,6 +381,117 @@ def gen_layered(seed: int, *, n_nodes: int, n_regs: int, n_pi: int, n_po: int,
 
 
 # ---------------------------------------------------------------------------
+# Template designs (the heavy-tailed configurations)
+# ---------------------------------------------------------------------------
+
+class _Net:
+    """Append-only node list for template construction."""
+
+    def __init__(self):
+        self.op, self.w, self.ins, self.param = [], [], [], []
+
+    def add(self, op, w, ins=(), param=0):
+        self.op.append(op)
+        self.w.append(w)
+        self.ins.append(list(ins) + [0] * (3 - len(ins)))
+        self.param.append(param)
+        return len(self.op) - 1
+
+    def set_in0(self, n, x):
+        self.ins[n][0] = x
+
+    def design(self, po, num_pi, name, meta):
+        nodes = np.zeros(len(self.op), dtype=NODE_DTYPE)
+        nodes["op"] = self.op
+        nodes["width"] = self.w
+        ins = np.asarray(self.ins, dtype=np.uint32)
+        nodes["in0"], nodes["in1"], nodes["in2"] = ins[:, 0], ins[:, 1], ins[:, 2]
+        nodes["param"] = np.asarray(self.param, dtype=np.uint64)
+        return Design(nodes, np.asarray(po, dtype=np.uint32), num_pi, name, meta)
+
+
+def gen_templates(seed: int, *, n_nodes: int, n_pi: int = 128, acc_share: float = 0.02,
+                  name: str = "templates") -> Design:
+    """Design assembled from seeded templates sharing the primary inputs:
+
+      pipelined datapath  k = 3..8 register stages of width 8/16/32, each stage
+                          mixing the previous stage with a primary-input slice
+                          (ADD/XOR/SUB, some MUX and AND masking); the last
+                          stage is an output, so a divergence reaches it within
+                          k cycles or dies out;
+      FSM                 8-bit state, next state chosen by a compare on an
+                          input slice between two update rules; the state,
+                          mixed with an input, is an output;
+      accumulator         32-bit acc <- acc + (a ^ b) observed only through
+                          acc == constant; a divergence stays in the state for
+                          the whole run without reaching an output.
+
+    Accumulators are added until they hold about ``acc_share`` of the bits
+    that can carry a fault.
+    """
+    st = Stream(sub_seed(seed, 1))
+    net = _Net()
+    pis = []
+    for i in range(n_pi):
+        pis.append(net.add(PI, 32, (), i))
+    po = []
+    acc_bits = 0
+    all_bits = 0
+
+    def pi_slice(w):
+        p = pis[st.below(n_pi)]
+        if w == 32:
+            return p
+        return net.add(SLICE, w, (p,), st.below(33 - w))
+
+    def count(n):
+        nonlocal all_bits
+        all_bits += net.w[n]
+        return n
+
+    while len(net.op) < n_nodes:
+        want_acc = acc_bits < acc_share * max(all_bits, 1)
+        kind = 2 if want_acc else (0 if st.uniform() < 0.8 else 1)
+        if kind == 0:
+            # pipelined datapath
+            w = (8, 16, 32)[st.below(3)]
+            k = 3 + st.below(6)
+            v = count(net.add(XOR, w, (pi_slice(w), pi_slice(w))))
+            for _ in range(k):
+                r = count(net.add(REG, w, (v,), 0))
+                op = (ADD, XOR, SUB, ADD, XOR)[st.below(5)]
+                v = count(net.add(op, w, (r, pi_slice(w))))
+                u = st.uniform()
+                if u < 0.15:
+                    m = net.add(CONST, w, (), int(st.u64() & mask_of(w)))
+                    v = count(net.add(AND, w, (v, m)))
+                elif u < 0.3:
+                    sel = count(net.add(ULT, 1, (pi_slice(8), net.add(CONST, 8, (), 200))))
+                    v = count(net.add(MUX, w, (sel, v, r)))
+            po.append(v)
+        elif kind == 1:
+            # FSM with 8-bit state
+            s = count(net.add(REG, 8, (0,), 0))
+            cond = count(net.add(EQ, 1, (pi_slice(2), net.add(CONST, 2, (), st.below(4)))))
+            a = count(net.add(ADD, 8, (s, net.add(CONST, 8, (), 1 + st.below(255)))))
+            b = count(net.add(XOR, 8, (s, pi_slice(8))))
+            nxt = count(net.add(MUX, 8, (cond, a, b)))
+            net.set_in0(s, nxt)
+            po.append(count(net.add(XOR, 8, (s, pi_slice(8)))))
+        else:
+            # accumulator observed through a compare
+            acc = count(net.add(REG, 32, (0,), 0))
+            fx = count(net.add(XOR, 32, (pis[st.below(n_pi)], pis[st.below(n_pi)])))
+            s2 = count(net.add(ADD, 32, (acc, fx)))
+            net.set_in0(acc, s2)
+            k = net.add(CONST, 32, (), int(st.u64() & 0xFFFFFFFF))
+            po.append(count(net.add(EQ, 1, (acc, k))))
+            acc_bits += 96
+    meta = {"acc_share": acc_share, "acc_bits": acc_bits, "fault_bits": all_bits}
+    return net.design(po, n_pi, name, meta)
+
+
+# ---------------------------------------------------------------------------
 # Stimulus and fault lists
 # ---------------------------------------------------------------------------
 
@@ -487,6 +598,45 @@ def tiny(seed: int | None = None, F: int = 2000, T: int = 128) -> Workload:
     d = gen_layered(s, n_nodes=8 + 16 + 120, n_regs=16, n_pi=8, n_po=4, n_levels=10,
                     widths=[1, 8, 16, 32], wweights=[1, 1, 1, 1], name="tiny")
     return Workload("tiny", d, gen_stimulus(s, d, T), gen_faults(s, d, F), T)
+
+
+def heavy_tailed(seed: int | None = None, F: int = 200000, T: int = 5000, n_nodes: int = 100000) -> Workload:
+    """Template design of 100,000 nodes (pipelines, FSMs, latent accumulators),
+    5,000 cycles, 200,000 stuck-at faults."""
+    s = config_seed(2) if seed is None else seed
+    d = gen_templates(s, n_nodes=n_nodes, name="heavy_tailed")
+    return Workload("heavy_tailed", d, gen_stimulus(s, d, T), gen_faults(s, d, F), T)
+
+
+def large(seed: int | None = None, F: int = 1000000, T: int = 10000, n_nodes: int = 200000) -> Workload:
+    """Template design of 200,000 nodes, 10,000 cycles, 1,000,000 stuck-at faults."""
+    s = config_seed(4) if seed is None else seed
+    d = gen_templates(s, n_nodes=n_nodes, name="large")
+    return Workload("large", d, gen_stimulus(s, d, T), gen_faults(s, d, F), T)
+
+
+def campaign(seed: int | None = None, n: int = 64, nodes=(1000, 50000), faults=(1000, 100000),
+             cycles=(500, 5000)) -> list[Workload]:
+    """Batched campaign: n independent layered designs with node counts
+    log-uniform in ``nodes``, register fraction uniform in 3..10 %, fault
+    counts log-uniform in ``faults`` and cycle counts uniform in ``cycles``.
+    Design k is seeded with the campaign seed + 1000 (k + 1)."""
+    s = config_seed(3) if seed is None else seed
+    st = Stream(sub_seed(s, 7))
+    out = []
+    for k in range(n):
+        sk = s + 1000 * (k + 1)
+        N = int(round(math.exp(math.log(nodes[0]) + st.uniform() * (math.log(nodes[1]) - math.log(nodes[0])))))
+        rf = 0.03 + 0.07 * st.uniform()
+        F = int(round(math.exp(math.log(faults[0]) + st.uniform() * (math.log(faults[1]) - math.log(faults[0])))))
+        T = cycles[0] + st.below(cycles[1] - cycles[0] + 1)
+        n_pi = min(128, max(8, N // 300))
+        d = gen_layered(sk, n_nodes=N, n_regs=max(1, int(rf * N)), n_pi=n_pi, n_po=max(1, n_pi // 2),
+                        n_levels=min(40, max(4, N // 100)), widths=[1, 8, 16, 32, 64], wweights=[2, 3, 2, 2, 1],
+                        name=f"campaign{k}")
+        U = 2 * int(fault_universe(d)[1].sum())
+        out.append(Workload(f"campaign{k}", d, gen_stimulus(sk, d, T), gen_faults(sk, d, min(F, U)), T))
+    return out
 
 
 def medium(seed: int | None = None, F: int = 50000, T: int = 1000, n_nodes: int = 20000) -> Workload:

@@ -1,0 +1,87 @@
+"""Batched campaigns: one captured graph over many designs' faults gives, per
+design, exactly the oracle's detect cycles and events, on every replay."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_16376_amd import riros
+from paper_2508_16376_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _load(ws):
+    ds = [riros.Design(w.design) for w in ws]
+    gs = [riros.Golden(d, w.stimulus, w.T) for d, w in zip(ds, ws)]
+    return ds, gs
+
+
+@pytest.fixture(scope="module")
+def small_campaign():
+    ws = W.campaign(seed=424242, n=8, nodes=(300, 4000), faults=(200, 3000), cycles=(50, 400))
+    refs = [oracle.fault_sim(w.design, w.stimulus, w.T, w.faults) for w in ws]
+    return ws, refs
+
+
+@pytest.mark.parametrize("kw", [{}, {"monitor_rate": 2.0}, {"light_cap": 4, "waves_per_cu": 3}])
+def test_small_campaign_matches_oracle_on_every_replay(small_campaign, kw):
+    import torch
+    ws, refs = small_campaign
+    ds, gs = _load(ws)
+    b = riros.Batch(ds, gs, [w.faults for w in ws], **kw)
+    for rep in range(3):
+        b.launch()
+        torch.cuda.synchronize()
+        x = torch.ones(1 << 20, device="cuda").sum().item()   # unrelated work between replays
+        assert x == float(1 << 20)
+        for i, w in enumerate(ws):
+            det, ev, cov = b.read(i)
+            np.testing.assert_array_equal(det, refs[i][0], err_msg=f"replay {rep} design {i}")
+            np.testing.assert_array_equal(ev, refs[i][1], err_msg=f"replay {rep} design {i}")
+            assert cov["total"] == w.faults.size
+            assert cov["detected"] == int((refs[i][0] != riros.UNDETECTED).sum())
+            assert cov["fault_cycles"] == oracle.fault_cycles(refs[i][0], w.T)
+            assert cov["events"] == int(refs[i][1].sum())
+
+
+def test_small_campaign_priorities_and_heavy_split(small_campaign):
+    ws, refs = small_campaign
+    ds, gs = _load(ws)
+    prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
+    theta = float(np.quantile(np.concatenate(prios), 0.9))
+    b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=4.0)
+    b.launch()
+    for i in range(len(ws)):
+        det, ev, _ = b.read(i)
+        np.testing.assert_array_equal(det, refs[i][0])
+        np.testing.assert_array_equal(ev, refs[i][1])
+
+
+def test_campaign_equals_single_design_runs(small_campaign):
+    ws, refs = small_campaign
+    ds, gs = _load(ws)
+    b = riros.Batch(ds, gs, [w.faults for w in ws])
+    b.launch()
+    for i, w in enumerate(ws):
+        det, ev, _ = b.read(i)
+        sdet, sev, _ = riros.fault_sim(ds[i], gs[i], w.faults, mode=riros.MODE_TWO_D)
+        np.testing.assert_array_equal(det, sdet)
+        np.testing.assert_array_equal(ev, sev)
+
+
+def test_full_size_campaign_sampled():
+    """The 64-design campaign at full size; per design, a sample of faults is
+    re-simulated by the oracle one by one, and coverage totals are consistent."""
+    ws = W.campaign()
+    ds, gs = _load(ws)
+    b = riros.Batch(ds, gs, [w.faults for w in ws], monitor_rate=2.0)
+    b.launch()
+    for i, w in enumerate(ws):
+        det, ev, cov = b.read(i)
+        idx = np.linspace(0, w.faults.size - 1, min(60, w.faults.size)).astype(np.int64)
+        odet, oev = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults[idx])
+        np.testing.assert_array_equal(det[idx], odet, err_msg=f"design {i}")
+        np.testing.assert_array_equal(ev[idx], oev, err_msg=f"design {i}")
+        assert cov["total"] == w.faults.size
+        assert cov["detected"] == int((det != riros.UNDETECTED).sum())
+        assert ((det < w.T) | (det == riros.UNDETECTED)).all()
