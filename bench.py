@@ -1,10 +1,12 @@
 """Fault-simulation throughput benchmark (fault-cycles per second) on one GPU.
 
-One step = one riros_fault_sim call over the whole fault list of the workload
-with inputs (design image, golden trace, fault list) already resident in
-device memory.  Prints one JSON line.
+One step = one pass of the whole hot path over the workload's fault list with
+inputs (design image, golden trace, fault list, predicted priorities) already
+resident in device memory: riros_fault_sim for one design, one campaign
+graph launch for the batched campaign.  Fault-cycles per fault are
+detect cycle + 1, or the cycle count if undetected.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload medium] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--workload medium|tiny|heavy_tailed|campaign|large]
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2508_16376_amd import riros  # noqa: E402
+from paper_2508_16376_amd import autotune, predictor, riros  # noqa: E402
 from paper_2508_16376_amd import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
@@ -31,9 +33,14 @@ BYTES_PER_FC = 8
 BYTES_PER_EVENT = 32
 
 WORKLOADS = {
-    "medium": ("medium: 20,000-node layered DAG (40 levels, 512 registers, widths 1-64), "
-               "1,000 cycles, 50,000 stuck-at faults, drop on", lambda: W.medium()),
-    "tiny": ("tiny: 144-node DAG, 128 cycles, 2,000 faults", lambda: W.tiny()),
+    "tiny": "tiny: 144-node DAG (120 operators, 16 registers), 128 cycles, 2,000 stuck-at faults",
+    "medium": "medium: 20,000-node layered DAG (40 levels, 512 registers, widths 1-64), 1,000 cycles, "
+              "50,000 stuck-at faults, drop on",
+    "heavy_tailed": "heavy-tailed: 100,000-node template design (pipelines, 8-bit FSMs, latent 32-bit "
+                    "accumulators), 5,000 cycles, 200,000 stuck-at faults",
+    "campaign": "batched campaign: 64 seeded designs (1k-50k nodes log-uniform, 3-10% registers), "
+                "1k-100k faults each (log-uniform), 500-5,000 cycles each, one graph launch",
+    "large": "large: 200,000-node template design, 10,000 cycles, 1,000,000 stuck-at faults",
 }
 
 
@@ -41,33 +48,141 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_mode(d, g, w, mode, steps, warmup, extra):
-    import torch
-    dev = torch.device("cuda:0")
-    F = w.faults.size
-    f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
-    det_dev = torch.empty(F, dtype=torch.int32, device=dev)
-    ev_dev = torch.empty(F, dtype=torch.int64, device=dev)
-    cov_dev = torch.zeros(4, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
-    prio = extra.pop("priority", None)
-    opts = riros.make_opts(mode, True, True, stream=stream, priority=prio, **extra)
-    for _ in range(warmup):
-        riros.fault_sim_device(d, g, f_dev, F, det_dev, ev_dev, cov_dev, opts)
-    torch.cuda.synchronize()
-    kms = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        riros.fault_sim_device(d, g, f_dev, F, det_dev, ev_dev, cov_dev, opts)
-        kms.append(riros.last_kernel_ms())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cov = cov_dev.cpu().numpy().astype(np.uint64)
-    det = det_dev.cpu().numpy().view(np.uint32).copy()
-    ev = ev_dev.cpu().numpy().view(np.uint64).copy()
-    return {"wall_s": wall, "kernel_ms": float(np.mean(kms)), "kernel_ms_all": kms,
-            "detected": int(cov[0]), "total": int(cov[1]), "fault_cycles": int(cov[2]), "events": int(cov[3]),
-            "detect": det, "events_arr": ev}
+def make_workload(name):
+    if name == "tiny":
+        return [W.tiny()]
+    if name == "medium":
+        return [W.medium()]
+    if name == "heavy_tailed":
+        return [W.heavy_tailed()]
+    if name == "large":
+        return [W.large()]
+    return W.campaign()
+
+
+def held_out_training_runs():
+    """Designs of the medium, heavy-tailed and campaign shapes with seeds other
+    than any benchmark workload; their plain-kernel event counts train the
+    predictor."""
+    ws = [W.medium(seed=7001, F=20000, T=1000), W.medium(seed=7002, F=20000, T=1000),
+          W.heavy_tailed(seed=7003, F=20000, T=1000, n_nodes=30000)]
+    ws += W.campaign(seed=7004, n=6, nodes=(1000, 20000), faults=(2000, 10000), cycles=(500, 2000))
+    runs = []
+    for w in ws:
+        d = riros.Design(w.design)
+        runs.append((d, riros.Golden(d, w.stimulus, w.T), w.faults))
+    return runs
+
+
+class Single:
+    """One design: steps are riros_fault_sim calls with device-resident I/O."""
+
+    def __init__(self, w):
+        import torch
+        self.w = w
+        self.d = riros.Design(w.design)
+        t = time.perf_counter()
+        self.g = riros.Golden(self.d, w.stimulus, w.T)
+        self.golden_s = time.perf_counter() - t
+        dev = torch.device("cuda:0")
+        F = w.faults.size
+        self.F = F
+        self.f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
+        self.det = torch.empty(F, dtype=torch.int32, device=dev)
+        self.ev = torch.empty(F, dtype=torch.int64, device=dev)
+        self.cov = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.prio_dev = None
+
+    def features(self):
+        return riros.features(self.d, self.g, self.w.faults)
+
+    def set_priority(self, pred):
+        import torch
+        self.prio_dev = None if pred is None else torch.from_numpy(np.ascontiguousarray(pred, np.float32)).cuda()
+
+    def run(self, mode, steps, warmup, kw):
+        import torch
+        opts = riros.make_opts(mode, True, True, stream=torch.cuda.current_stream(),
+                               priority=self.prio_dev if mode == riros.MODE_TWO_D else None, **kw)
+        for _ in range(warmup):
+            riros.fault_sim_device(self.d, self.g, self.f_dev, self.F, self.det, self.ev, self.cov, opts)
+        torch.cuda.synchronize()
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            riros.fault_sim_device(self.d, self.g, self.f_dev, self.F, self.det, self.ev, self.cov, opts)
+            kms.append(riros.last_kernel_ms())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        c = self.cov.cpu().numpy().astype(np.int64)
+        return {"wall_s": wall, "kernel_ms": float(np.mean(kms)), "fault_cycles": int(c[2]), "events": int(c[3]),
+                "detected": int(c[0]), "detect": [self.det.cpu().numpy().view(np.uint32).copy()],
+                "events_arr": [self.ev.cpu().numpy().view(np.uint64).copy()]}
+
+
+class Campaign:
+    """Many designs: a plain step runs riros_fault_sim per design; a batched
+    step is one graph launch of the whole campaign."""
+
+    def __init__(self, ws):
+        self.ws = ws
+        self.ds = [riros.Design(w.design) for w in ws]
+        t = time.perf_counter()
+        self.gs = [riros.Golden(d, w.stimulus, w.T) for d, w in zip(self.ds, ws)]
+        self.golden_s = time.perf_counter() - t
+
+    def features(self):
+        return [riros.features(d, g, w.faults) for d, g, w in zip(self.ds, self.gs, self.ws)]
+
+    def run_plain(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            for d, g, w in zip(self.ds, self.gs, self.ws):
+                riros.fault_sim(d, g, w.faults, mode=riros.MODE_PLAIN)
+        kms, res = [], None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            k = 0.0
+            res = []
+            for d, g, w in zip(self.ds, self.gs, self.ws):
+                res.append(riros.fault_sim(d, g, w.faults, mode=riros.MODE_PLAIN))
+                k += riros.last_kernel_ms()
+            kms.append(k)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # a plain step includes host-side fault upload and result download per
+        # design; its rate uses the summed kernel time instead of the wall
+        return {"wall_s": wall, "kernel_ms": float(np.mean(kms)), "kernel_bound": True,
+                "fault_cycles": sum(r[2]["fault_cycles"] for r in res), "events": sum(r[2]["events"] for r in res),
+                "detected": sum(r[2]["detected"] for r in res), "detect": [r[0] for r in res],
+                "events_arr": [r[1] for r in res]}
+
+    def run_batch(self, steps, warmup, kw, prios):
+        import torch
+        b = riros.Batch(self.ds, self.gs, [w.faults for w in self.ws], prios, **kw)
+        s = torch.cuda.current_stream()
+        for _ in range(warmup):
+            b.launch(s)
+        torch.cuda.synchronize()
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.launch(s)
+            kms.append(riros.last_kernel_ms())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res = [b.read(i) for i in range(len(self.ws))]
+        b.close()
+        return {"wall_s": wall, "kernel_ms": float(np.mean(kms)),
+                "fault_cycles": sum(r[2]["fault_cycles"] for r in res), "events": sum(r[2]["events"] for r in res),
+                "detected": sum(r[2]["detected"] for r in res), "detect": [r[0] for r in res],
+                "events_arr": [r[1] for r in res]}
+
+
+def rate(r, steps):
+    if r.get("kernel_bound"):
+        return r["fault_cycles"] / (r["kernel_ms"] * 1e-3)
+    return r["fault_cycles"] * steps / r["wall_s"]
 
 
 def main():
@@ -77,6 +192,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-predictor", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the fault list would be "
@@ -87,58 +204,134 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    desc, make = WORKLOADS[args.workload]
     t = time.perf_counter()
-    w = make()
+    ws = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: generated in {time.perf_counter() - t:.2f}s")
-    d = riros.Design(w.design)
-    t = time.perf_counter()
-    g = riros.Golden(d, w.stimulus, w.T)
-    golden_s = time.perf_counter() - t
-    log(f"[bench] golden trace: {golden_s:.3f}s")
+    multi = args.workload == "campaign"
+    job = Campaign(ws) if multi else Single(ws[0])
+    log(f"[bench] golden traces: {job.golden_s:.3f}s")
 
-    plain = run_mode(d, g, w, riros.MODE_PLAIN, args.steps, args.warmup, {})
-    log(f"[bench] plain: kernel {plain['kernel_ms']:.3f} ms, wall {plain['wall_s']:.3f}s for {args.steps} steps")
-    twod = run_mode(d, g, w, riros.MODE_TWO_D, args.steps, args.warmup, {"monitor_rate": 2.0})
-    log(f"[bench] two_d: kernel {twod['kernel_ms']:.3f} ms, wall {twod['wall_s']:.3f}s for {args.steps} steps")
-    same = bool(np.array_equal(plain["detect"], twod["detect"]) and np.array_equal(plain["events_arr"], twod["events_arr"]))
-    best = twod
-    best_name = "two_d"
+    # Plain fault-parallel kernel.
+    if multi:
+        plain = job.run_plain(args.steps, args.warmup)
+    else:
+        plain = job.run(riros.MODE_PLAIN, args.steps, args.warmup, {})
+    log(f"[bench] plain: kernel {plain['kernel_ms']:.3f} ms, rate {rate(plain, args.steps):.4g} FC/s")
+
+    # Predictor: trained on held-out designs' plain-kernel events.
+    pred_info = {}
+    preds = None
+    if not args.no_predictor:
+        t = time.perf_counter()
+        runs = held_out_training_runs()
+        x, y = predictor.samples_from_runs(runs)
+        data_s = time.perf_counter() - t
+        t = time.perf_counter()
+        wts, losses = predictor.train(x, y, epochs=8, batch=4096)
+        train_s = time.perf_counter() - t
+        del runs
+        t = time.perf_counter()
+        feats = job.features()
+        if multi:
+            preds = [riros.mlp_predict(wts, f) for f in feats]
+        else:
+            preds = riros.mlp_predict(wts, feats)
+        infer_s = time.perf_counter() - t
+        true = np.concatenate([np.log2(1 + e.astype(np.float64)) for e in plain["events_arr"]])
+        err = predictor.load_error(np.concatenate(preds) if multi else preds, true)
+        pred_info = {"train_samples": int(x.shape[0]), "train_data_s": data_s, "train_s": train_s,
+                     "features_and_inference_s": infer_s, "final_loss": float(losses[-1]),
+                     "spearman": err["spearman"], "mean_abs_log2": err["mean_abs_log2"]}
+        log(f"[bench] predictor: spearman {err['spearman']:.3f}, mean |dlog2| {err['mean_abs_log2']:.3f}")
+
+    # Autotuned two-dimensional schedule.
+    tuner = autotune.Autotuner()
+    t = time.perf_counter()
+    if args.no_tune:
+        params = dict(autotune.DEFAULT)
+    elif multi:
+        params = tuner.tune_batch([w.design for w in ws], job.ds, job.gs, [w.faults for w in ws], preds)
+    else:
+        params = tuner.tune_single(ws[0].design, job.d, job.g, ws[0].faults, preds, ws[0].T)
+    tune_s = time.perf_counter() - t
+    log(f"[bench] autotuner: {params} in {tune_s:.2f}s")
+
+    if multi:
+        allp = None if preds is None else np.concatenate(preds)
+        static = job.run_batch(args.steps, args.warmup,
+                               autotune.batch_kwargs(dict(params, heavy_quantile=None)), None)
+        best = job.run_batch(args.steps, args.warmup, autotune.batch_kwargs(params, allp), preds)
+    else:
+        job.set_priority(None)
+        static = job.run(riros.MODE_TWO_D, args.steps, args.warmup,
+                         autotune.single_kwargs(dict(params, heavy_quantile=None)))
+        job.set_priority(preds)
+        best = job.run(riros.MODE_TWO_D, args.steps, args.warmup, autotune.single_kwargs(params, preds))
+    log(f"[bench] two_d static: kernel {static['kernel_ms']:.3f} ms; with predictor: {best['kernel_ms']:.3f} ms")
+
+    same = all(np.array_equal(a, b) for a, b in zip(plain["detect"], best["detect"])) and \
+        all(np.array_equal(a, b) for a, b in zip(plain["events_arr"], best["events_arr"])) and \
+        all(np.array_equal(a, b) for a, b in zip(static["detect"], best["detect"]))
 
     FC, E = best["fault_cycles"], best["events"]
-    ms_per_step = best["wall_s"] / args.steps * 1e3
-    value = FC * args.steps / best["wall_s"]
+    value = rate(best, args.steps)
     alg_bytes = BYTES_PER_FC * FC + BYTES_PER_EVENT * E
     achieved = alg_bytes / (best["kernel_ms"] * 1e-3) / 1e9
-
+    total_faults = sum(w.faults.size for w in ws)
     out = {
         "metric": "fault-cycles/sec, plain vs batched+predictor, bit-exact detect cycles",
         "value": value, "unit": "fault-cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
-        "config": {"workload": desc, "mode": best_name, "faults": int(w.faults.size), "cycles": w.T,
-                   "nodes": w.design.num_nodes},
+        "ms_per_step": best["wall_s"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "designs": len(ws), "faults": int(total_faults),
+                   "mode": "two-dimensional, predictor-ordered, autotuned" + (", one graph launch" if multi else "")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_twod_a+k_twod_b", "kernel_ms": best["kernel_ms"],
                      "alg_bytes_per_launch": alg_bytes},
-        "plain": {"fault_cycles_per_s": FC * args.steps / plain["wall_s"], "kernel_ms": plain["kernel_ms"]},
-        "two_d": {"fault_cycles_per_s": FC * args.steps / twod["wall_s"], "kernel_ms": twod["kernel_ms"]},
-        "plain_equals_two_d": same,
-        "golden_s": golden_s,
-        "fault_cycles": FC, "events": E, "detected": best["detected"],
+        "plain": {"fault_cycles_per_s": rate(plain, args.steps), "kernel_ms": plain["kernel_ms"]},
+        "two_d_static": {"fault_cycles_per_s": rate(static, args.steps), "kernel_ms": static["kernel_ms"]},
+        "two_d_predictor": {"fault_cycles_per_s": value, "kernel_ms": best["kernel_ms"]},
+        "speedup_vs_plain": rate(best, args.steps) / rate(plain, args.steps),
+        "autotuned": {"params": params, "tune_s": tune_s},
+        "predictor": pred_info,
+        "results_identical_across_modes": bool(same),
+        "golden_s": job.golden_s, "fault_cycles": FC, "events": E, "detected": best["detected"],
     }
 
     if not args.no_cpu_baseline:
         import oracle
         nt = oracle.default_threads()
-        t = time.perf_counter()
-        odet, oev = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults, variant=1, nthreads=nt)
-        cpu_s = time.perf_counter() - t
-        ofc = oracle.fault_cycles(odet, w.T)
-        exact = bool(np.array_equal(odet, best["detect"]) and np.array_equal(oev, best["events_arr"]))
-        out["cpu_baseline"] = {"value": ofc / cpu_s, "unit": "fault-cycles/s", "cores": nt, "kind": "oracle",
-                               "sample": f"whole workload ({w.faults.size} faults), oracle O1, {cpu_s:.2f}s wall"}
+        # Parity: every fault where the oracle finishes quickly, a bounded
+        # sample otherwise; the same oracle run is the CPU baseline.
+        # The sample is a seeded uniform draw grown until about 15 s of oracle
+        # time (the whole list when it finishes sooner).
+        exact = True
+        cpu_fc, cpu_s, nsample = 0, 0.0, 0
+        budget = 15.0
+        for i, w in enumerate(ws):
+            if cpu_s > budget:
+                break
+            G = oracle.golden(w.design, w.stimulus, w.T)
+            perm = np.argsort(W.counter_values(0xBA5E + i, 0, w.faults.size))
+            done = 0
+            n = min(w.faults.size, 1000)
+            while done < w.faults.size and cpu_s < budget:
+                idx = np.sort(perm[done:done + n])
+                t = time.perf_counter()
+                odet, oev = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults[idx], G=G, variant=1, nthreads=nt)
+                dt = time.perf_counter() - t
+                cpu_s += dt
+                cpu_fc += oracle.fault_cycles(odet, w.T)
+                nsample += idx.size
+                done += idx.size
+                exact &= bool(np.array_equal(odet, best["detect"][i][idx]) and
+                              np.array_equal(oev, best["events_arr"][i][idx]))
+                n = int(min(w.faults.size - done, max(n, n * (budget - cpu_s) / max(dt, 1e-3) * 0.5)))
+            del G
+        out["cpu_baseline"] = {"value": cpu_fc / cpu_s, "unit": "fault-cycles/s", "cores": nt, "kind": "oracle",
+                               "sample": f"{nsample} of {total_faults} faults of the same workload (seeded uniform "
+                                         f"draw), oracle O1 (divergent nodes only), {cpu_s:.2f}s wall on {nt} threads"}
         out["parity"] = "bit-exact" if exact else "MISMATCH"
         if not exact:
             log("[bench] detect/events differ from the oracle")

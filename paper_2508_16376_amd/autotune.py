@@ -1,0 +1,137 @@
+"""Autotuner for the two-dimensional schedule.
+
+Chooses, per design (or campaign) and fault population, the parameters that
+decide where work runs: the events-per-cycle threshold of the light-lane
+monitor, the light-lane capacity, the number of resident wavefronts per
+compute unit, and (with a predictor) the predicted-load quantile above which
+faults start on the structural path.  The paper fixes its overload threshold
+by hand (Sec. V-A); here candidates are timed and the fastest kept, one
+parameter at a time (coordinate descent), with the result cached by design
+hash.  Candidates run on the whole fault list: a sample with fewer faults than
+lanes would hide the contention of the structural path (one fault per
+wavefront) and pick thresholds that fail at full scale.  No parameter changes
+a result, only time.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+
+import numpy as np
+
+from . import riros
+
+SPACE = {
+    "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
+    "light_cap": [4, 8],
+    "waves_per_cu": [8, 12, 16],
+    "heavy_quantile": [None, 0.999, 0.99],
+}
+DEFAULT = {"monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "heavy_quantile": None}
+
+
+def design_key(design, T: int, F: int, with_priority: bool) -> str:
+    h = hashlib.sha1(np.ascontiguousarray(design.nodes).tobytes())
+    h.update(np.ascontiguousarray(design.po).tobytes())
+    return f"{h.hexdigest()[:16]}-T{T}-F{F}-p{int(with_priority)}"
+
+
+def _opts(p, priority):
+    theta = math.inf
+    if priority is not None and p["heavy_quantile"] is not None:
+        theta = float(np.quantile(priority, p["heavy_quantile"]))
+    return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
+            "theta": theta}
+
+
+def _time_single(d, g, faults, priority, p, reps=2):
+    kw = _opts(p, priority)
+    best = math.inf
+    for _ in range(reps):
+        riros.fault_sim(d, g, faults, mode=riros.MODE_TWO_D, priority=priority, with_events=False, **kw)
+        best = min(best, riros.last_kernel_ms())
+    return best
+
+
+class Autotuner:
+    def __init__(self, cache_path: str | None = None):
+        self.cache_path = cache_path
+        self.cache: dict[str, dict] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+        self.log: list[dict] = []
+
+    def _save(self):
+        if self.cache_path:
+            with open(self.cache_path, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+
+    def _descend(self, measure, with_priority: bool):
+        best = dict(DEFAULT)
+        best_t = measure(best)
+        self.log.append({"params": dict(best), "ms": best_t})
+        seen = {tuple(sorted(best.items(), key=lambda kv: kv[0]))}
+        for name, values in SPACE.items():
+            if name == "heavy_quantile" and not with_priority:
+                continue
+            for v in values:
+                cand = dict(best)
+                cand[name] = v
+                key = tuple(sorted(cand.items(), key=lambda kv: kv[0]))
+                if key in seen:
+                    continue
+                seen.add(key)
+                t = measure(cand)
+                self.log.append({"params": dict(cand), "ms": t})
+                if t < best_t:
+                    best, best_t = cand, t
+        return best, best_t
+
+    def tune_single(self, design_np, d, g, faults, priority=None, T=None):
+        """Parameters for riros_fault_sim(mode=TWO_D) on this design and fault list."""
+        key = design_key(design_np, T or 0, faults.size, priority is not None)
+        if key in self.cache:
+            return self.cache[key]["params"]
+        ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
+        best, t = self._descend(lambda p: _time_single(d, g, faults, ps, p, reps=1), priority is not None)
+        self.cache[key] = {"params": best, "ms": t}
+        self._save()
+        return best
+
+    def tune_batch(self, designs_np, ds, gs, fault_lists, priorities=None):
+        """Parameters for a campaign (riros_batch_create)."""
+        h = hashlib.sha1()
+        for dn, fl in zip(designs_np, fault_lists):
+            h.update(np.ascontiguousarray(dn.nodes).tobytes())
+            h.update(np.int64(fl.size).tobytes())
+        key = f"batch-{h.hexdigest()[:16]}-p{int(priorities is not None)}"
+        if key in self.cache:
+            return self.cache[key]["params"]
+        prs = None if priorities is None else [np.ascontiguousarray(p, dtype=np.float32) for p in priorities]
+        allp = None if prs is None else np.concatenate(prs)
+
+        def measure(p):
+            kw = _opts(p, allp)
+            b = riros.Batch(ds, gs, fault_lists, prs, **kw)
+            b.launch()
+            b.read(0)
+            t = riros.last_kernel_ms()
+            b.close()
+            return t
+
+        best, t = self._descend(measure, priorities is not None)
+        self.cache[key] = {"params": best, "sample_ms": t}
+        self._save()
+        return best
+
+
+def batch_kwargs(params, priorities_concat=None):
+    """riros.Batch keyword arguments for tuned parameters."""
+    return _opts(params, priorities_concat)
+
+
+def single_kwargs(params, priority=None):
+    return _opts(params, priority)

@@ -1,0 +1,39 @@
+"""Host logic of the autotuner: coordinate descent over the schedule space."""
+from paper_2508_16376_amd import autotune
+
+
+def test_descent_finds_the_coordinatewise_minimum():
+    calls = []
+
+    def cost(p):
+        calls.append(dict(p))
+        c = abs(p["monitor_rate"] - 4.0) + (0 if p["light_cap"] == 4 else 1) + abs(p["waves_per_cu"] - 16) / 4
+        c += 0 if p["heavy_quantile"] == 0.99 else 0.5
+        return c
+
+    t = autotune.Autotuner()
+    best, bt = t._descend(cost, with_priority=True)
+    assert best == {"monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "heavy_quantile": 0.99}
+    assert bt == 0
+    # every candidate is a point of the space, and no point is timed twice
+    keys = [tuple(sorted(c.items(), key=lambda kv: kv[0])) for c in calls]
+    assert len(keys) == len(set(keys))
+    for c in calls:
+        for k, v in c.items():
+            assert v in autotune.SPACE[k] or v == autotune.DEFAULT[k]
+
+
+def test_no_predictor_keeps_every_fault_light_first():
+    t = autotune.Autotuner()
+    best, _ = t._descend(lambda p: 1.0 if p["heavy_quantile"] is None else 0.0, with_priority=False)
+    assert best["heavy_quantile"] is None
+    kw = autotune.single_kwargs(best, None)
+    assert kw["theta"] == float("inf")
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tune.json")
+    t = autotune.Autotuner(path)
+    t.cache["k"] = {"params": dict(autotune.DEFAULT)}
+    t._save()
+    assert autotune.Autotuner(path).cache["k"]["params"] == autotune.DEFAULT
