@@ -11,9 +11,11 @@ detect cycle + 1, or the cycle count if undetected.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -46,6 +48,53 @@ WORKLOADS = {
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest():
+    """Digest of the HIP sources; a counter summary taken on other sources no
+    longer describes the kernels that run."""
+    h = hashlib.sha1()
+    src = os.path.join(ROOT, "paper_2508_16376_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per fault-simulation pass (FETCH_SIZE and WRITE_SIZE counters,
+    each scaled by the same counter's reading for a copy of known size), from
+    the committed counter summary of this workload; None when there is none or
+    it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+): `?([^`\s]+)`?", line)
+            if m:
+                fields[m.group(1)] = m.group(2)
+    if fields.get("kernel_sources") != kernel_source_digest() or "hbm_bytes_per_pass" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_pass"])
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration():
+    """One device-to-device copy of COPY_BYTES bytes (read COPY_BYTES, write
+    COPY_BYTES): the known-size reference for the HBM byte counters."""
+    import torch
+    src = torch.full((COPY_BYTES // 8,), 7, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    assert int(dst[-1]) == 7
+    print(json.dumps({"copy_bytes": COPY_BYTES}))
 
 
 def make_workload(name):
@@ -194,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-predictor", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one copy of known size (for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the fault list would be "
@@ -204,6 +255,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     t = time.perf_counter()
     ws = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: generated in {time.perf_counter() - t:.2f}s")
@@ -286,7 +340,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "designs": len(ws), "faults": int(total_faults),
                    "mode": "two-dimensional, predictor-ordered, autotuned" + (", one graph launch" if multi else "")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_twod_a+k_twod_b", "kernel_ms": best["kernel_ms"],
                      "alg_bytes_per_launch": alg_bytes},
         "plain": {"fault_cycles_per_s": rate(plain, args.steps), "kernel_ms": plain["kernel_ms"]},
