@@ -134,7 +134,11 @@ typedef struct {
     int32_t light_cap;     /* TWO_D: per-lane divergent-node capacity, 4, 8 or 16
                               (0 = 8); a lane that overflows hands its fault to
                               the structural path */
-    int32_t chunk;         /* reserved, must be 0 */
+    int32_t unified;       /* TWO_D: 1 = a wavefront whose lanes have run out of
+                              light work takes handed-over faults while the
+                              others still run light work (the structural path
+                              then needs LDS in every wavefront of launch A);
+                              0 = handed-over faults wait for launch B */
     float monitor_rate;    /* TWO_D: a light fault averaging more than this many
                               events per cycle after its first 8 cycles moves to
                               the structural path (0 = never) */
@@ -156,7 +160,7 @@ typedef struct {
  * value differs from the golden machine (Sec. II-B, concurrent fault
  * simulation); with drop = 1 the count stops after the detect cycle.
  * cov (may be NULL) receives totals.  Results do not depend on mode, priority,
- * theta, chunk or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
+ * theta, light_cap, unified, monitor_rate or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
  * bit >= width, stuck > 1, unknown mode, design/golden mismatch), RIROS_ENOMEM,
  * RIROS_EDEVICE. */
 int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,

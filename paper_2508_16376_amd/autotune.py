@@ -1,10 +1,11 @@
 """Autotuner for the two-dimensional schedule.
 
 Chooses, per design (or campaign) and fault population, the parameters that
-decide where work runs: the events-per-cycle threshold of the light-lane
-monitor, the light-lane capacity, the number of resident wavefronts per
-compute unit, and (with a predictor) the predicted-load quantile above which
-faults start on the structural path.  The paper fixes its overload threshold
+decide where work runs: whether idle wavefronts take handed-over faults
+during the light launch (the unified schedule), the events-per-cycle
+threshold of the light-lane monitor, the light-lane capacity, the number of
+resident wavefronts per compute unit, and (with a predictor) the
+predicted-load quantile above which faults start on the structural path.  The paper fixes its overload threshold
 by hand (Sec. V-A); here candidates are timed and the fastest kept, one
 parameter at a time (coordinate descent), with the result cached by design
 hash.  Candidates run on the whole fault list: a sample with fewer faults than
@@ -24,12 +25,13 @@ import numpy as np
 from . import riros
 
 SPACE = {
+    "unified": [1, 0],
     "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
     "light_cap": [4, 8],
     "waves_per_cu": [8, 12, 16],
     "heavy_quantile": [None, 0.999, 0.99],
 }
-DEFAULT = {"monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "heavy_quantile": None}
+DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -43,7 +45,7 @@ def _opts(p, priority):
     if priority is not None and p["heavy_quantile"] is not None:
         theta = float(np.quantile(priority, p["heavy_quantile"]))
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
-            "theta": theta}
+            "unified": p.get("unified", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):

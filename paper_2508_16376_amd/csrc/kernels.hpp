@@ -27,9 +27,10 @@ struct DevDesign {
     uint32_t bp_rows;
 };
 
-// Golden trace in three layouts: row-major G[t][n] (per-cycle sweeps of the
-// structural path), node-major Gn[n][t] (a lane following one node over
-// consecutive cycles hits the same cache line), and bit-planes
+// Golden trace in three layouts: row-major G[t][n] (what the golden kernel
+// writes and riros_golden_read returns), node-major Gn[n][t] (read by every
+// fault kernel: a node evaluated in consecutive cycles stays in one cache
+// line for eight cycles), and bit-planes
 // Bp[row][w] with row = bp_off[n] + bit, word w holding cycles 64w..64w+63.
 struct GoldenView {
     const uint64_t* G;
@@ -63,7 +64,7 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
 // Bytes of dynamic LDS the plain kernel needs for a design.
 size_t plain_lds_bytes(const DevDesign& d);
 
-hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* G, uint32_t T,
+hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* Gn, uint32_t T,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
                               hipStream_t s);

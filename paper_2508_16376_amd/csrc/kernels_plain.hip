@@ -108,7 +108,7 @@ size_t plain_lds_bytes(const DevDesign& d)
     return wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
 }
 
-__global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ G,
+__global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gn,
                                                     uint32_t T, const riros_fault* __restrict__ faults,
                                                     uint32_t F, int drop, PlainWorkspace ws,
                                                     uint32_t* __restrict__ detect_out,
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
     for (uint32_t fi = blockIdx.x; fi < F; fi += gridDim.x) {
         uint32_t det;
         uint64_t ev;
-        wave_sim_fault(d, G, T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(d, Gn, T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
         if (threadIdx.x == 0) {
             detect_out[fi] = det;
             if (events_out) events_out[fi] = ev;
@@ -143,7 +143,7 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* G, uint32_t T,
+hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* Gn, uint32_t T,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
                               hipStream_t s)
@@ -152,7 +152,7 @@ hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* G, uint32_t T,
     hipError_t e = hipFuncSetAttribute((const void*)k_fault_plain,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, G, T, faults, F, drop, ws,
+    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, Gn, T, faults, F, drop, ws,
                        detect, events);
     return hipGetLastError();
 }

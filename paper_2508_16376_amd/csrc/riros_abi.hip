@@ -320,9 +320,9 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
     if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
         return set_err(RIROS_EINVAL, "unknown mode");
-    if (opts->waves_per_cu < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f) ||
+    if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
-        return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, chunk != 0, bad monitor_rate, or "
+        return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, or "
                                      "light_cap not 0, 4, 8 or 16)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
@@ -393,7 +393,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
         riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_dev};
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
-        HIP_TRY(riros::launch_fault_plain(d->dev, g->G, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
+        HIP_TRY(riros::launch_fault_plain(d->dev, g->Gn, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
                                           d_events, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
@@ -412,7 +412,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.monitor_rate = opts->monitor_rate;
         p.theta = opts->theta;
         p.light_cap = opts->light_cap;
-        p.chunk = opts->chunk;
+        p.unified = opts->unified;
         p.waves_per_cu = opts->waves_per_cu;
         p.num_cu = d->num_cu;
         std::string err;
@@ -423,10 +423,9 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     g_ev_valid = true;
 
     if (!on_dev && opts->mode == RIROS_MODE_TWO_D && d->twod.ctr) {
-        uint32_t words[8];
-        HIP_TRY(hipMemcpyAsync(words, d->twod.ctr, sizeof words, hipMemcpyDeviceToHost, s), "counter read");
-        HIP_TRY(hipStreamSynchronize(s), "counter sync");
-        if (words[5]) return set_err(RIROS_EDEVICE, "a handed-over fault was never published");
+        std::string err;
+        const int rc = riros::twod_check(d->twod, s, err);
+        if (rc) return set_err(rc, err);
     }
     riros_coverage* cov_dst = on_dev ? cov : d->d_cov;
     if (cov) HIP_TRY(riros::launch_coverage(d_detect, d_events, F, T, cov_dst, s), "coverage");
@@ -621,7 +620,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (n == 0 || n > 65536) return set_err(RIROS_EINVAL, "n must be in 1..65536");
     if (opts->mode != RIROS_MODE_TWO_D || opts->io_on_device)
         return set_err(RIROS_EINVAL, "campaigns run in RIROS_MODE_TWO_D with host-side inputs");
-    if (opts->waves_per_cu < 0 || opts->chunk != 0 || !(opts->monitor_rate >= 0.f) ||
+    if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
@@ -741,6 +740,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     std::string err;
     int rc = riros::order_batch(b->tw, d_pr, b->F, opts->theta, &p.order, b->cap_stream, err);
     if (rc) return fail(rc, err);
+    p.heavy = d_pr != nullptr && !(opts->theta > 3.0e38f);
+    p.unified = opts->unified;
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);
     if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign preparation: ") + hipGetErrorString(e));

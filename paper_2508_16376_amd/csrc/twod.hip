@@ -10,9 +10,15 @@
 //      structural path when the frontier outgrows the lane's capacity, or when
 //      the fault's events per cycle exceed a threshold (a monitor in the spirit
 //      of the paper's execution-time-share monitor, Sec. IV-C);
-//   launch B: the handed-over faults, one per wavefront, from cycle 0.
-// No wavefront ever waits for another.  Where a fault runs never changes its
-// result.
+//   launch A, phase 3 (unified schedule, optional): a wavefront whose lanes
+//      have run out of light work takes handed-over faults while the other
+//      wavefronts are still in phase 2, so long faults start on the
+//      structural path as soon as they are handed over (the paper overlaps
+//      phases by letting idle workers steal across them, Sec. IV-D);
+//   launch B: the handed-over faults nobody took in launch A, one per
+//      wavefront, from cycle 0.
+// No wavefront waits for another's work, only (boundedly) for new work to
+// appear.  Where a fault runs never changes its result.
 #include <hipcub/hipcub.hpp>
 
 #include "device_common.hpp"
@@ -23,14 +29,17 @@ namespace riros {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
+// Counters that different parties hammer sit on separate 128-byte lines, so
+// that phase-3 polling never slows the light lanes' atomics.
 struct TwoDCounters {
-    uint32_t light_head;   // next index into the light queue
-    uint32_t esc_count;    // faults handed from light lanes to the heavy path
-    uint32_t heavy_head;   // next index into the up-front heavy queue
-    uint32_t n_heavy;      // faults placed on the heavy queue up front
-    uint32_t esc_head;     // next handed-over fault to simulate
-    uint32_t error;        // set if a handed-over fault was never published
-    uint32_t pad[2];
+    alignas(128) uint32_t light_head;   // next index into the light queue
+    uint32_t heavy_head;                // next index into the up-front heavy queue
+    uint32_t n_heavy;                   // faults placed on the heavy queue up front
+    alignas(128) uint32_t esc_count;    // faults handed from light lanes to the heavy path
+    alignas(128) uint32_t esc_head;     // launch B: next handed-over fault to look at
+    uint32_t light_done;                // wavefronts of launch A that finished their light work
+    uint32_t error;                     // unused (kept zero)
+    alignas(128) uint32_t esc_take;     // phase-3 tickets (launch A)
 };
 
 // Lane-private sets, held in registers: every index below is a compile-time
@@ -149,7 +158,10 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
                             uint64_t* __restrict__ events_out, uint32_t lanes, uint32_t rate_num)
 {
-    constexpr int CR = C / 2;
+    // Register next-state deltas: a pipeline keeps one per divergent stage.
+    // Batched lanes hold their design's pointers in registers, so they keep
+    // fewer (occupancy stays at three or four wavefronts per SIMD).
+    constexpr int CR = BATCH ? C / 2 : (C == 4 ? 4 : (C == 8 ? 6 : 8));
     constexpr uint32_t kPre = 4;
     const uint32_t lane = threadIdx.x & 63;
     // One design: uniform for the whole wave.  Batched: per lane, per fault.
@@ -308,7 +320,11 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         if (!esc_now && rate_num && t >= 8 && ev * 4 > (uint64_t)rate_num * (t + 1)) esc_now = true;
         if (esc_now) {
             const uint32_t slot = atomicAdd(&ctr->esc_count, 1u);
-            esc[slot] = fi;
+            // A phase-3 wavefront may be waiting for this entry (kNone until
+            // written).  The entry itself is the whole message, so a relaxed
+            // device-scope store suffices; release or acquire at device scope
+            // would write back or invalidate the whole L2 on every access.
+            __hip_atomic_store(&esc[slot], fi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             fi = kNone;
             continue;
         }
@@ -345,13 +361,87 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
         const uint32_t k = src.did[fi];
         const DevDesign dd = src.td[k];
         const GoldenView gg = src.tg[k];
-        wave_sim_fault(dd, gg.G, gg.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(dd, gg.Gn, gg.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     } else {
-        wave_sim_fault(src.d, src.g.G, src.g.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(src.d, src.g.Gn, src.g.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     }
     if (threadIdx.x == 0) {
         detect_out[fi] = det;
         if (events_out) events_out[fi] = ev;
+    }
+}
+
+// Phase 3: take handed-over faults while launch A runs.  The wavefront first
+// counts itself as done with light work, then takes a ticket: the ticket-th
+// handed-over fault is its next one.  It waits (polling its own entry, with
+// backoff) until that fault is published, and simulates it; or until every
+// wavefront of the launch is done with light work and the list ended before
+// its ticket (then it leaves); or until a bounded idle time has passed (then
+// it leaves its ticket, and launch B simulates the fault if it comes).  A
+// simulated entry is overwritten with kDone, which launch B skips.
+constexpr uint32_t kDone = 0xFFFFFFFEu;
+// Tickets never exceed the hand-overs plus one per wavefront of launch A
+// (each holds at most one unfilled ticket), and launch A never has more than
+// kTicketPad wavefronts: the list has F + kTicketPad entries, all kNone at the
+// start of a run.
+constexpr uint32_t kTicketPad = 8192;
+// Idle polls back off from one to 32 maximal sleeps (about 3 to 100 us); the
+// limit counts sleeps (about a second in all).
+constexpr uint32_t kIdleLimit = 1u << 18;
+
+template <bool BATCH>
+__device__ void drain_handover(const DesignSrc& src, const riros_fault* __restrict__ faults, uint32_t F,
+                               TwoDCounters* ctr, uint32_t* esc, int drop, const WaveLds& s, Slot* slots,
+                               uint64_t* regs, uint64_t& stamp0, uint32_t* __restrict__ detect_out,
+                               uint64_t* __restrict__ events_out)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    // This wavefront's hand-overs all returned their slots before this point,
+    // so they are performed before the increment below.
+    if (lane == 0) __hip_atomic_fetch_add(&ctr->light_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t idle = 0;
+    for (;;) {
+        uint32_t fi = kNone, ticket = 0;
+        bool leave = false;
+        if (lane == 0) {
+            ticket = atomicAdd(&ctr->esc_take, 1u);
+            uint32_t backoff = 1;
+            // (ticket >= F + kTicketPad cannot happen; leave rather than read past the list.)
+            leave = ticket >= F + kTicketPad;
+            while (!leave) {
+                // Device-scope relaxed atomics throughout: the entry itself is
+                // the message, and acquire or release at device scope would
+                // write back or invalidate the L2 on every poll.
+                const uint32_t v = __hip_atomic_load(&esc[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v != kNone) {
+                    fi = v;
+                    break;
+                }
+                // light_done first: once it is complete, esc_count read after
+                // it is final (the fence only waits for the load).
+                const uint32_t done = __hip_atomic_load(&ctr->light_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const uint32_t c = __hip_atomic_load(&ctr->esc_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ticket < c) continue;   // reserved: the store follows at once
+                if (done >= gridDim.x) {
+                    leave = true;
+                    break;
+                }
+                idle += backoff;
+                if (idle > kIdleLimit) {
+                    leave = true;
+                    break;
+                }
+                for (uint32_t k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(127);
+                backoff = min(backoff * 2, 32u);
+            }
+        }
+        fi = __shfl(fi, 0, 64);
+        ticket = __shfl(ticket, 0, 64);
+        if (__shfl((int)leave, 0, 64)) break;
+        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out);
+        if (lane == 0) __hip_atomic_store(&esc[ticket], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        idle = 0;
     }
 }
 
@@ -360,36 +450,47 @@ struct MaxShape {
     uint32_t N, L, R;
 };
 
-template <int C, bool BATCH>
+// STRUCT = false: the launch has no structural work (no heavy prefix and no
+// phase 3), so it needs no LDS and its occupancy is bounded by registers
+// alone.  STRUCT = true: phase 1 over the heavy prefix (possibly empty), and
+// phase 3 when `unified`.
+template <int C, bool BATCH, bool STRUCT>
 __global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
                                                uint32_t F, const uint32_t* __restrict__ order, TwoDCounters* ctr,
                                                uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-                                               uint32_t rate_num,
+                                               uint32_t rate_num, int unified,
                                                uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
 {
-    extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
-    wave_lds_clear(s, mx.N, mx.L, mx.R);
-    __syncthreads();
-    Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
-    uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
-    uint64_t stamp0 = *ws.stamp_dev;
-    const uint32_t nh = ctr->n_heavy;
-    // Phase 1: heavy faults placed up front.
-    for (;;) {
-        uint32_t idx = 0;
-        if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
-        idx = __shfl(idx, 0, 64);
-        if (idx >= nh) break;
-        heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
-                         events_out);
+    if constexpr (STRUCT) {
+        extern __shared__ uint32_t lds[];
+        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+        wave_lds_clear(s, mx.N, mx.L, mx.R);
+        __syncthreads();
+        Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
+        uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
+        uint64_t stamp0 = *ws.stamp_dev;
+        const uint32_t nh = ctr->n_heavy;
+        // Phase 1: heavy faults placed up front.
+        for (;;) {
+            uint32_t idx = 0;
+            if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
+            idx = __shfl(idx, 0, 64);
+            if (idx >= nh) break;
+            heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
+                             events_out);
+        }
+        // Phase 2: light faults, one per lane; each wavefront takes at most
+        // its share of lanes so that light faults spread over every wavefront.
+        const uint32_t nlight = F - nh;
+        const uint32_t lanes = min(64u, max(1u, (nlight + gridDim.x - 1) / gridDim.x));
+        light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
+                              events_out, lanes, rate_num);
+        if (unified)
+            drain_handover<BATCH>(src, faults, F, ctr, esc, drop, s, slots, regs, stamp0, detect_out, events_out);
+    } else {
+        const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
+        light_phase<C, BATCH>(src, faults, F, order, ctr, esc, drop, detect_out, events_out, lanes, rate_num);
     }
-    // Phase 2: light faults, one per lane; each wavefront takes at most its
-    // share of lanes so that light faults spread over every wavefront.
-    const uint32_t nlight = F - nh;
-    const uint32_t lanes = min(64u, max(1u, (nlight + gridDim.x - 1) / gridDim.x));
-    light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
-                          events_out, lanes, rate_num);
 }
 
 // Launch B: the faults handed over in launch A (their list is complete).
@@ -413,7 +514,9 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
         if (threadIdx.x == 0) idx = atomicAdd(&ctr->esc_head, 1u);
         idx = __shfl(idx, 0, 64);
         if (idx >= n) break;
-        heavy_one<BATCH>(src, esc[idx], faults, drop, s, slots, regs, stamp0, detect_out, events_out);
+        const uint32_t fi = esc[idx];
+        if (fi == kDone) continue;   // simulated in launch A (phase 3)
+        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out);
     }
 }
 
@@ -443,7 +546,7 @@ __global__ void k_count_heavy(const float* __restrict__ sorted_desc, uint32_t n,
 
 __global__ void k_zero_counters(TwoDCounters* ctr)
 {
-    if (threadIdx.x < sizeof(TwoDCounters) / 4) ((uint32_t*)ctr)[threadIdx.x] = 0;
+    for (uint32_t i = threadIdx.x; i < sizeof(TwoDCounters) / 4; i += blockDim.x) ((uint32_t*)ctr)[i] = 0;
 }
 
 // Reset the per-run counters, keeping the heavy-queue length fixed when the
@@ -456,6 +559,8 @@ __global__ void k_reset_run_counters(TwoDCounters* ctr)
         ctr->heavy_head = 0;
         ctr->esc_head = 0;
         ctr->error = 0;
+        ctr->light_done = 0;
+        ctr->esc_take = 0;
     }
 }
 
@@ -506,7 +611,7 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     TwoDLayout l{};
     size_t o = 0;
     l.ctr = o; o += up(sizeof(TwoDCounters));
-    l.esc = o; o += up((size_t)F * 4);
+    l.esc = o; o += up(((size_t)F + kTicketPad) * 4);
     l.order = o; o += up((size_t)F * 4);
     l.idx = o; o += up((size_t)F * 4);
     l.keys_out = o; o += up((size_t)F * 4);
@@ -516,20 +621,60 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     return l;
 }
 
+// Persistent launches never exceed what can be resident at once (phase 3
+// waits for every wavefront of its launch to finish light work).
+static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want)
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu <= 0 || cus <= 0)
+        return std::min(want, kTicketPad);
+    return std::max(1u, std::min<uint32_t>(std::min(want, kTicketPad), (uint32_t)per_cu * (uint32_t)cus));
+}
+
+template <int C, bool BATCH>
+static const void* kernel_a(bool structural)
+{
+    return structural ? (const void*)k_twod_a<C, BATCH, true> : (const void*)k_twod_a<C, BATCH, false>;
+}
+
+static const void* kernel_a_any(int cap, bool batch, bool structural)
+{
+    if (batch) return cap == 4 ? kernel_a<4, true>(structural) : (cap == 16 ? kernel_a<16, true>(structural) : kernel_a<8, true>(structural));
+    return cap == 4 ? kernel_a<4, false>(structural) : (cap == 16 ? kernel_a<16, false>(structural) : kernel_a<8, false>(structural));
+}
+
+static uint32_t twod_blocks_a(int cap, bool batch, bool structural, const MaxShape& mx, uint32_t want)
+{
+    const size_t lds = structural ? wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t) : 0;
+    const void* k = kernel_a_any(cap, batch, structural);
+    if (structural && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return std::min(want, kTicketPad);
+    return resident_blocks(k, lds, want);
+}
+
 template <int C, bool BATCH>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
-                                const uint32_t* order, TwoDCounters* ctr, uint32_t* esc, int drop,
-                                const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
+                                const uint32_t* order, bool heavy, int unified, TwoDCounters* ctr, uint32_t* esc,
+                                int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
                                 uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
     const size_t lds = wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
-    hipError_t e = hipFuncSetAttribute((const void*)k_twod_a<C, BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_twod_a<C, BATCH>), dim3(blocks), dim3(64), lds, s, src, mx, faults, F, order, ctr, esc,
-                       drop, ws, rate_num, detect, events);
+    const bool structural = heavy || unified;
+    const uint32_t ba = twod_blocks_a(C, BATCH, structural, mx, blocks);
+    if (unified)
+        hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
+    if (structural) {
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ba), dim3(64), lds, s, src, mx, faults, F, order, ctr,
+                           esc, drop, ws, rate_num, unified, detect, events);
+    } else {
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ba), dim3(64), 0, s, src, mx, faults, F, order, ctr,
+                           esc, drop, ws, rate_num, 0, detect, events);
+    }
     hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(blocks), dim3(64), lds, s, src, mx, faults, ctr, esc, drop, ws, span,
                        detect, events);
     e = hipGetLastError();
@@ -539,14 +684,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 
 template <bool BATCH>
 static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
-                                  uint32_t F, const uint32_t* order, TwoDCounters* ctr, uint32_t* esc, int drop,
-                                  const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
+                                  uint32_t F, const uint32_t* order, bool heavy, int unified, TwoDCounters* ctr,
+                                  uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
                                   uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
     switch (cap) {
-    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
     }
 }
 
@@ -614,24 +759,27 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     DesignSrc src{d, gw, nullptr, nullptr, nullptr};
     const MaxShape mx{d.N, d.L, d.R};
     const uint64_t span = (uint64_t)F * gw.T + 1;
-    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, ctr, esc, drop, heavy_ws, span,
-                                          blocks, rate_num, detect, events, s);
+    const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
+    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, ctr, esc, drop,
+                                          heavy_ws, span, blocks, rate_num, detect, events, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     return RIROS_OK;
 }
 
-hipError_t prepare_twod_batch(const BatchPlan& b)
+hipError_t prepare_twod_batch(BatchPlan& b)
 {
     const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
     hipError_t e = hipSuccess;
     auto attr = [&](const void* f) {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    attr((const void*)k_twod_a<4, true>);
-    attr((const void*)k_twod_a<8, true>);
-    attr((const void*)k_twod_a<16, true>);
+    attr((const void*)k_twod_a<4, true, true>);
+    attr((const void*)k_twod_a<8, true, true>);
+    attr((const void*)k_twod_a<16, true, true>);
     attr((const void*)k_twod_b<true>);
+    if (e == hipSuccess)
+        b.blocks_a = twod_blocks_a(b.light_cap, true, b.heavy || b.unified, MaxShape{b.Nmax, b.Lmax, b.Rmax}, b.blocks);
     return e;
 }
 
@@ -663,11 +811,26 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     DesignSrc src{b.td_host0, b.tg_host0, b.td, b.tg, b.did};
     const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
     const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
-    switch (b.light_cap) {
-    case 4: hipLaunchKernelGGL((k_twod_a<4, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
-    case 16: hipLaunchKernelGGL((k_twod_a<16, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
-    default: hipLaunchKernelGGL((k_twod_a<8, true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, b.F, b.order, ctr, esc, b.drop, b.ws, b.rate_num, b.detect, b.events); break;
+#define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
+    hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(64), L, s, src, mx, b.faults, b.F, b.order, \
+                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events)
+    if (b.unified)
+        hipLaunchKernelGGL(k_fill_u32, dim3((b.F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, b.F + kTicketPad,
+                           kNone);
+    if (b.heavy || b.unified) {
+        switch (b.light_cap) {
+        case 4: RIROS_LAUNCH_A(4, true, lds); break;
+        case 16: RIROS_LAUNCH_A(16, true, lds); break;
+        default: RIROS_LAUNCH_A(8, true, lds); break;
+        }
+    } else {
+        switch (b.light_cap) {
+        case 4: RIROS_LAUNCH_A(4, false, 0); break;
+        case 16: RIROS_LAUNCH_A(16, false, 0); break;
+        default: RIROS_LAUNCH_A(8, false, 0); break;
+        }
     }
+#undef RIROS_LAUNCH_A
     hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
                        b.span, b.detect, b.events);
     hipError_t e = hipGetLastError();
@@ -676,6 +839,21 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_coverage, dim3(b.n), dim3(256), 0, s, b.detect, b.events, b.off, b.tg, b.cov);
     return hipGetLastError();
+}
+
+int twod_check(const TwoDWorkspace& ws, hipStream_t s, std::string& err)
+{
+    TwoDCounters c;
+    if (hipMemcpyAsync(&c, ws.ctr, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        err = "counter read";
+        return RIROS_EDEVICE;
+    }
+    if (c.esc_head < c.esc_count) {
+        err = "handed-over faults left unsimulated";
+        return RIROS_EDEVICE;
+    }
+    return RIROS_OK;
 }
 
 void twod_free(TwoDWorkspace& ws)

@@ -15,27 +15,32 @@ namespace riros {
 struct TwoDWorkspace {
     void* mem = nullptr;
     size_t bytes = 0;
-    void* ctr = nullptr;   // device counters of the last run (error flag at word 5)
+    void* ctr = nullptr;   // device counters of the last run
 };
 
 struct TwoDParams {
     float theta = INFINITY;
     int light_cap = 0;
-    int chunk = 0;
+    int unified = 0;            // waves out of light work take handed-over faults during launch A
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
 };
 
-// Light kernel over the faults whose priority is <= theta (all faults when
-// priority is NULL), in descending priority order, then the heavy kernel over
-// the faults above theta and the faults the light lanes handed over.
-// heavy_ws / heavy_blocks: per-wave workspace of the heavy kernel.
+// Launch A: the faults whose priority is above theta on the structural path
+// first, then the rest one per lane in descending priority order (all faults
+// in list order when priority is NULL), then (unified) handed-over faults;
+// launch B: the handed-over faults left.  heavy_ws / heavy_blocks: per-wave
+// workspace of the structural path and the grid size.
 int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gv,
              const riros_fault* faults, const float* priority, uint32_t F, int drop,
              const TwoDParams& p, PlainWorkspace heavy_ws, uint32_t heavy_blocks,
              uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
              std::string& err);
+
+// Synchronises s and checks the last run's counters: every handed-over fault
+// was simulated (RIROS_EDEVICE otherwise).
+int twod_check(const TwoDWorkspace& ws, hipStream_t s, std::string& err);
 
 // Batched campaign: many designs in one persistent launch.  The device tables
 // td/tg hold each design's image and golden views; did[f] is fault f's design,
@@ -51,10 +56,13 @@ struct BatchPlan {
     uint32_t Nmax = 0, Lmax = 0, Rmax = 0;
     const riros_fault* faults = nullptr;
     const uint32_t* order = nullptr;
+    bool heavy = false;       // a heavy prefix exists (priorities with a finite threshold)
+    int unified = 0;          // phase 3 in launch A (see riros_sim_opts.unified)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;
-    uint32_t blocks = 0;
+    uint32_t blocks = 0;      // launch B (and workspace) grid
+    uint32_t blocks_a = 0;    // launch A grid (at most what is resident at once)
     uint64_t span = 0;        // an upper bound of the stamps one block can use
     PlainWorkspace ws{};
     uint32_t* detect = nullptr;
@@ -63,7 +71,7 @@ struct BatchPlan {
 };
 
 // Kernel attributes (outside any capture).
-hipError_t prepare_twod_batch(const BatchPlan& b);
+hipError_t prepare_twod_batch(BatchPlan& b);
 // Order the concatenated faults by priority (NULL: keep them in order); sets
 // the heavy prefix.  Not capturable.
 int order_batch(TwoDWorkspace& ws, const float* priority, uint32_t F, float theta, const uint32_t** order,

@@ -54,7 +54,7 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 // ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform) and the
 // event count (wave total).  Must be called by all 64 lanes of a one-wave
 // workgroup (it uses __syncthreads as the wave's LDS fence).
-__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ G, uint32_t T,
+__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gn, uint32_t T,
                                       const riros_fault f, int drop, const WaveLds& s,
                                       Slot* __restrict__ slots, uint64_t* __restrict__ regs,
                                       uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
@@ -71,7 +71,9 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     __syncthreads();
     for (uint32_t t = 0; t < T; ++t) {
         const uint64_t stamp = stamp0 + t + 1;
-        const uint64_t* g = G + (size_t)t * N;
+        // Node-major golden values: a node evaluated in consecutive cycles
+        // reads one cache line per eight cycles.
+        auto gold = [&](uint32_t n) { return Gn[(size_t)n * T + t]; };
         const uint64_t* rst = regs + (size_t)(t & 1) * R;
         uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
         // Cycle start: registers whose D diverged last cycle are scheduled.
@@ -137,7 +139,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     // Record (descriptor + fan-out ranges) and the node's golden value in one round trip,
                     // then operands and the first fan-out entries in a second.
                     const NodeRec x = d.rec[n];
-                    const uint64_t gv = g[n];
+                    const uint64_t gv = gold(n);
                     const uint32_t nf = x.fo1 - x.fo0;
                     const uint64_t pk0 = nf > 0 ? d.fo_pk[x.fo0] : 0;
                     const uint64_t pk1 = nf > 1 ? d.fo_pk[x.fo0 + 1] : 0;
@@ -156,7 +158,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         for (int k = 0; k < 3; ++k) {
                             if (k < ar) {
                                 const Slot sl = slots[ins[k]];
-                                const uint64_t gx = g[ins[k]];
+                                const uint64_t gx = gold(ins[k]);
                                 const bool dv = sl.stamp == stamp;
                                 xs[k] = dv ? sl.v : gx;
                                 din |= dv;

@@ -9,11 +9,12 @@ def test_descent_finds_the_coordinatewise_minimum():
         calls.append(dict(p))
         c = abs(p["monitor_rate"] - 4.0) + (0 if p["light_cap"] == 4 else 1) + abs(p["waves_per_cu"] - 16) / 4
         c += 0 if p["heavy_quantile"] == 0.99 else 0.5
+        c += 0 if p["unified"] == 0 else 0.25
         return c
 
     t = autotune.Autotuner()
     best, bt = t._descend(cost, with_priority=True)
-    assert best == {"monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "heavy_quantile": 0.99}
+    assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "heavy_quantile": 0.99}
     assert bt == 0
     # every candidate is a point of the space, and no point is timed twice
     keys = [tuple(sorted(c.items(), key=lambda kv: kv[0])) for c in calls]

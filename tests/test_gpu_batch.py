@@ -23,7 +23,8 @@ def small_campaign():
     return ws, refs
 
 
-@pytest.mark.parametrize("kw", [{}, {"monitor_rate": 2.0}, {"light_cap": 4, "waves_per_cu": 3}])
+@pytest.mark.parametrize("kw", [{}, {"monitor_rate": 2.0}, {"light_cap": 4, "waves_per_cu": 3},
+                                {"monitor_rate": 1.0, "unified": 1}])
 def test_small_campaign_matches_oracle_on_every_replay(small_campaign, kw):
     import torch
     ws, refs = small_campaign
@@ -49,12 +50,15 @@ def test_small_campaign_priorities_and_heavy_split(small_campaign):
     ds, gs = _load(ws)
     prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
     theta = float(np.quantile(np.concatenate(prios), 0.9))
-    b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=4.0)
-    b.launch()
-    for i in range(len(ws)):
-        det, ev, _ = b.read(i)
-        np.testing.assert_array_equal(det, refs[i][0])
-        np.testing.assert_array_equal(ev, refs[i][1])
+    for unified in (0, 1):
+        b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=4.0, unified=unified)
+        for _ in range(2):
+            b.launch()
+            for i in range(len(ws)):
+                det, ev, _ = b.read(i)
+                np.testing.assert_array_equal(det, refs[i][0])
+                np.testing.assert_array_equal(ev, refs[i][1])
+        b.close()
 
 
 def test_campaign_equals_single_design_runs(small_campaign):
@@ -74,7 +78,7 @@ def test_full_size_campaign_sampled():
     re-simulated by the oracle one by one, and coverage totals are consistent."""
     ws = W.campaign()
     ds, gs = _load(ws)
-    b = riros.Batch(ds, gs, [w.faults for w in ws], monitor_rate=2.0)
+    b = riros.Batch(ds, gs, [w.faults for w in ws], monitor_rate=2.0, unified=1)
     b.launch()
     for i, w in enumerate(ws):
         det, ev, cov = b.read(i)

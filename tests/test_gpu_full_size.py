@@ -52,7 +52,7 @@ def test_full_size_against_stored_oracle_sample(name):
     theta = float(np.quantile(pred, 0.99))
     s = torch.cuda.current_stream()
     opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio, theta=theta,
-                           monitor_rate=1.0, light_cap=8, waves_per_cu=12)
+                           monitor_rate=1.0, light_cap=8, waves_per_cu=12, unified=1)
     det, ev, cov = _device_run(d, g, w, opts)
     np.testing.assert_array_equal(det[idx], odet)
     np.testing.assert_array_equal(ev[idx], oev)

@@ -221,10 +221,32 @@ def test_two_d_monitor_hand_over(small, rate):
         _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, monitor_rate=rate)
 
 
+@pytest.mark.parametrize("rate", [0.5, 4.0])
+@pytest.mark.parametrize("light_cap", [4, 8])
+def test_two_d_unified_schedule(small, rate, light_cap):
+    """Launch-A wavefronts that run out of light work take handed-over faults
+    while others still run light work; results are identical."""
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, monitor_rate=rate,
+               light_cap=light_cap, unified=1)
+
+
+def test_two_d_unified_with_heavy_prefix_and_small_grid(small):
+    prio = (W.counter_values(12, 0, small.faults.size) >> np.uint64(40)).astype(np.float32) / np.float32(1 << 24)
+    for wpc in (1, 4):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, priority=prio,
+               theta=0.9, monitor_rate=1.0, unified=1, waves_per_cu=wpc)
+
+
+def test_two_d_unified_medium_full_size():
+    w = W.medium()
+    _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, monitor_rate=2.0, light_cap=4, unified=1)
+
+
 def test_two_d_rejects_bad_options(tiny):
     d = riros.Design(tiny.design)
     g = riros.Golden(d, tiny.stimulus, tiny.T)
-    for kw in ({"chunk": 3}, {"monitor_rate": -1.0}, {"light_cap": 5}):
+    for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}):
         with pytest.raises(riros.RirosError):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
