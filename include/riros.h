@@ -68,14 +68,21 @@ typedef struct {
     uint64_t param;      /* CONST value, PI column, REG reset value, shift amount or SLICE low bit */
 } riros_node;
 
-/* A single stuck-at fault: bit `bit` of node `site` is forced to `stuck` in
- * every cycle (the forcing applies to the node's value as seen by its users
- * and by output comparison; a register's next-state write is not forced). */
+/* A single fault on bit `bit` of node `site` (a wire fault sits on the node
+ * driving the wire, a register fault on the register's node, Sec. IV-A).
+ * stuck 0 or 1: stuck-at, the bit is forced to `stuck` in every cycle.
+ * stuck RIROS_FAULT_FLIP: the bit is inverted in cycle t0 only; on a register
+ * this is a single-event upset of the stored state, which then evolves
+ * normally (the paper's unified injection admits other fault models through
+ * the faulty-value function, Sec. IV-A and V-A).  Either way the effect
+ * applies to the node's value as seen by its users and by output comparison;
+ * a register's next-state write is not altered. */
+#define RIROS_FAULT_FLIP 2
 typedef struct {
     uint32_t site;
     uint8_t bit;         /* < width(site) */
-    uint8_t stuck;       /* 0 or 1 */
-    uint16_t reserved;
+    uint8_t stuck;       /* 0, 1 or RIROS_FAULT_FLIP */
+    uint16_t t0;         /* RIROS_FAULT_FLIP: the cycle of the flip (no effect if >= T); else ignored */
 } riros_fault;
 
 typedef struct {
@@ -152,7 +159,7 @@ typedef struct {
     uint64_t events;        /* sum of per-fault event counts */
 } riros_coverage;
 
-/* Fault-simulate F single stuck-at faults against the golden trace.
+/* Fault-simulate F single faults (stuck-at or bit flip) against the golden trace.
  * detect[F] receives the first cycle in which any primary output of the
  * faulty machine differs from the golden trace, or RIROS_UNDETECTED.
  * events[F] (may be NULL) receives the fault's bad-gate evaluations: node n in
@@ -161,7 +168,7 @@ typedef struct {
  * simulation); with drop = 1 the count stops after the detect cycle.
  * cov (may be NULL) receives totals.  Results do not depend on mode, priority,
  * theta, light_cap, unified, monitor_rate or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
- * bit >= width, stuck > 1, unknown mode, design/golden mismatch), RIROS_ENOMEM,
+ * bit >= width, stuck > 2, unknown mode, design/golden mismatch), RIROS_ENOMEM,
  * RIROS_EDEVICE. */
 int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
                     const riros_sim_opts* opts, uint32_t* detect, uint64_t* events,
@@ -183,7 +190,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
  * level / deepest level; fewest registers from the site to an output (capped
  * at 16, -1 if none); log2(site width); toggle rate of the site bit over the
  * golden trace (changes / (T-1)); fraction of cycles in which the site bit
- * differs from the stuck value.  faults/out are device pointers when
+ * differs from the stuck value (a flip: 1/T if t0 < T, else 0).  faults/out are device pointers when
  * io_on_device (asynchronous on stream), else host pointers.  Errors as for
  * riros_fault_sim. */
 int riros_features(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F, float* out,

@@ -11,7 +11,8 @@ For a fault (site s, bit b, stuck v) over a golden trace of T cycles:
   3  log2(width of s);
   4  toggle rate of bit b of s: cycles t in 1..T-1 where it differs from
      cycle t-1, divided by max(1, T-1);
-  5  excitation rate: cycles where bit b differs from v, divided by T.
+  5  excitation rate: cycles where bit b differs from v, divided by T (a bit
+     flip is excited once, in its cycle t0, if t0 < T).
 
 Plain Python graph walks and numpy over the oracle's golden trace.
 """
@@ -21,7 +22,7 @@ from collections import deque
 
 import numpy as np
 
-from paper_2508_16376_amd.workloads import ARITY, CONST, PI, REG
+from paper_2508_16376_amd.workloads import ARITY, CONST, FLIP, PI, REG
 
 CONE_CAP = 1024
 DEPTH_CAP = 16
@@ -139,7 +140,7 @@ def features(design, G: np.ndarray, faults: np.ndarray) -> np.ndarray:
             cone_cache[s] = cone_size(design, s, comb_users, reg_users)
         bits = ((G[:, s] >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
         toggles = int(np.count_nonzero(bits[1:] != bits[:-1]))
-        excited = int(np.count_nonzero(bits != v))
+        excited = int(int(f["t0"]) < T) if v == FLIP else int(np.count_nonzero(bits != v))
         out[i] = [np.log2(1.0 + cone_cache[s]), lvl[s] / maxl, float(rdep[s]),
                   np.log2(float(design.nodes["width"][s])), toggles / max(1, T - 1), excited / T]
     return out

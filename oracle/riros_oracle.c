@@ -25,6 +25,11 @@
  *     every cycle (a wire fault sits on the node driving the wire, a register
  *     fault on the register's node, Sec. IV-A); a forced register is forced on
  *     read, its next-state write is never forced;
+ *   - a bit flip (stuck == 2, cycle t0) inverts bit b of node s in cycle t0
+ *     only: a transient fault model through the same injection point (the
+ *     paper's unified injection supports other fault models by changing the
+ *     faulty-value function, Sec. IV-A and V-A); on a register it is a
+ *     single-event upset of the stored state, which then evolves normally;
  *   - a fault is detected in the first cycle in which any primary output
  *     differs from the golden value (Sec. II-B); otherwise it is undetected
  *     (0xFFFFFFFF);
@@ -57,9 +62,11 @@ typedef struct {
 
 typedef struct {
     uint32_t site;
-    uint8_t bit, stuck;
-    uint16_t pad;
+    uint8_t bit, stuck;   /* stuck: 0 or 1 (stuck-at), O_FLIP (bit flip in cycle t0) */
+    uint16_t t0;
 } o_fault;
+
+#define O_FLIP 2
 
 #define O_UNDET 0xFFFFFFFFu
 
@@ -100,9 +107,11 @@ static uint64_t o_apply(const o_node* nd, const o_node* all, uint64_t a, uint64_
     return r & o_mask(nd->width);
 }
 
-static uint64_t o_force(uint64_t v, const o_fault* f)
+/* The fault's effect on its site's value in cycle t. */
+static uint64_t o_force(uint64_t v, const o_fault* f, uint32_t t)
 {
     uint64_t bit = 1ull << f->bit;
+    if (f->stuck == O_FLIP) return t == f->t0 ? (v ^ bit) : v;
     return f->stuck ? (v | bit) : (v & ~bit);
 }
 
@@ -259,7 +268,7 @@ static void o0_one(const o_design* d, const uint64_t* stim, uint32_t T, const ui
         for (uint32_t i = 0; i < N; ++i) {
             uint32_t n = d->topo[i];
             uint64_t v = o_value(d, n, val, state, row);
-            if (n == f->site) v = o_force(v, f);
+            if (n == f->site) v = o_force(v, f, t);
             val[n] = v;
         }
         for (uint32_t n = 0; n < N; ++n) {
@@ -425,7 +434,7 @@ static void o1_one(const o_design* d, const o1_graph* gr, const uint64_t* stim, 
                     }
                     v = o_apply(x, d->nd, op[0], op[1], op[2]);
                 }
-                if (n == f->site) v = o_force(v, f);
+                if (n == f->site) v = o_force(v, f, t);
                 int div_out = v != g[n];
                 if (div_in || div_out) ev++;
                 if (!div_out) continue;
@@ -538,7 +547,7 @@ int oracle_fault_sim(int variant, const void* nodes, uint32_t N, const uint32_t*
     if (rc) return rc;
     const o_fault* fl = (const o_fault*)faults;
     for (uint32_t i = 0; i < F; ++i)
-        if (fl[i].site >= N || fl[i].bit >= d.nd[fl[i].site].width || fl[i].stuck > 1) {
+        if (fl[i].site >= N || fl[i].bit >= d.nd[fl[i].site].width || fl[i].stuck > O_FLIP) {
             o_release(&d);
             return -4;
         }

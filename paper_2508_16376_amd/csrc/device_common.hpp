@@ -57,9 +57,13 @@ __device__ __forceinline__ uint64_t apply_op(const Desc& d, uint64_t x0, uint64_
 
 // Stuck-at forcing of one bit (Sec. IV-A: the faulty value replaces the
 // computed one at the injected node).
-__device__ __forceinline__ uint64_t force_bit(uint64_t v, uint32_t bit, uint32_t stuck)
+// The fault's effect on its site's value in cycle t: a stuck-at fault
+// (stuck 0 or 1) forces bit `bit` in every cycle; a bit flip (RIROS_FAULT_FLIP)
+// inverts it in cycle t0 only.
+__device__ __forceinline__ uint64_t apply_fault(uint64_t v, uint32_t bit, uint32_t stuck, uint32_t t, uint32_t t0)
 {
     const uint64_t m = 1ull << bit;
+    if (stuck == RIROS_FAULT_FLIP) return t == t0 ? (v ^ m) : v;
     return stuck ? (v | m) : (v & ~m);
 }
 

@@ -64,7 +64,7 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
 // Bytes of dynamic LDS the plain kernel needs for a design.
 size_t plain_lds_bytes(const DevDesign& d);
 
-hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* Gn, uint32_t T,
+hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
                               hipStream_t s);

@@ -39,7 +39,7 @@ __global__ void k_features(DevDesign d, GoldenView gw, const float4* __restrict_
         toggles += __popcll(ch);
         prev_top = x >> 63;
     }
-    const uint64_t excited = f.stuck ? (uint64_t)T - ones : ones;
+    const uint64_t excited = f.stuck == RIROS_FAULT_FLIP ? (uint64_t)(f.t0 < T) : (f.stuck ? (uint64_t)T - ones : ones);
     float* o = out + (size_t)i * kMlpFeatures;
     o[0] = nf.x;
     o[1] = nf.y;

@@ -105,17 +105,18 @@ hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t
 // ---------------------------------------------------------------------------
 size_t plain_lds_bytes(const DevDesign& d)
 {
-    return wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
+    return wave_lds_words(d.N, d.L, d.R, kRecCacheBig) * sizeof(uint32_t);
 }
 
 __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gn,
-                                                    uint32_t T, const riros_fault* __restrict__ faults,
+                                                    const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
+                                                    const riros_fault* __restrict__ faults,
                                                     uint32_t F, int drop, PlainWorkspace ws,
                                                     uint32_t* __restrict__ detect_out,
                                                     uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
+    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R, kRecCacheBig);
     wave_lds_clear(s, d.N, d.L, d.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
     for (uint32_t fi = blockIdx.x; fi < F; fi += gridDim.x) {
         uint32_t det;
         uint64_t ev;
-        wave_sim_fault(d, Gn, T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(d, Gn, Bp, T, TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
         if (threadIdx.x == 0) {
             detect_out[fi] = det;
             if (events_out) events_out[fi] = ev;
@@ -143,7 +144,7 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* Gn, uint32_t T,
+hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
                               hipStream_t s)
@@ -152,7 +153,7 @@ hipError_t launch_fault_plain(const DevDesign& d, const uint64_t* Gn, uint32_t T
     hipError_t e = hipFuncSetAttribute((const void*)k_fault_plain,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, Gn, T, faults, F, drop, ws,
+    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, g.Gn, g.Bp, g.T, g.TW, faults, F, drop, ws,
                        detect, events);
     return hipGetLastError();
 }
@@ -167,7 +168,7 @@ __global__ void k_validate(DevDesign d, const riros_fault* __restrict__ faults, 
     bool b = false;
     if (i < F) {
         const riros_fault f = faults[i];
-        b = f.site >= d.N || f.stuck > 1 || f.bit >= d.uwidth[f.site < d.N ? f.site : 0];
+        b = f.site >= d.N || f.stuck > RIROS_FAULT_FLIP || f.bit >= d.uwidth[f.site < d.N ? f.site : 0];
     }
     const uint64_t bal = __ballot(b);
     if (lane_id() == 0 && bal) atomicAdd(bad, (uint32_t)__popcll(bal));

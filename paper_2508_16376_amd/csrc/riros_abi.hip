@@ -343,7 +343,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (!on_dev) {
         for (uint32_t i = 0; i < F; ++i) {
             const riros_fault& f = faults[i];
-            if (f.site >= im.N || f.stuck > 1 || f.bit >= d->img.desc[im.u2i[f.site]].width) {
+            if (f.site >= im.N || f.stuck > RIROS_FAULT_FLIP || f.bit >= d->img.desc[im.u2i[f.site]].width) {
                 char buf[128];
                 std::snprintf(buf, sizeof buf, "fault %u: site %u bit %u stuck %u invalid", i, f.site, f.bit,
                               f.stuck);
@@ -393,7 +393,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
         riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_dev};
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
-        HIP_TRY(riros::launch_fault_plain(d->dev, g->Gn, T, d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
+        HIP_TRY(riros::launch_fault_plain(d->dev, g->view(), d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
                                           d_events, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
@@ -401,9 +401,10 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     } else {
         const size_t lds = riros::plain_lds_bytes(d->dev);
         if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");
-        const int lds_limit = (int)std::max<size_t>(1, (160 * 1024) / lds);
+        // The launches clamp their grids to what is resident at once; the
+        // light launch may need no LDS at all, so LDS does not cap this.
         int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 12;
-        wpc = std::min(std::min(wpc, lds_limit), 32);
+        wpc = std::min(wpc, 32);
         const uint32_t heavy_blocks = (uint32_t)d->num_cu * (uint32_t)wpc;
         int rc = ensure_plain_ws(d, heavy_blocks, s);
         if (rc) return rc;
@@ -472,7 +473,7 @@ int riros_features(riros_design d, riros_golden g, const riros_fault* faults, ui
     }
     for (uint32_t i = 0; i < F; ++i) {
         const riros_fault& f = faults[i];
-        if (f.site >= im.N || f.stuck > 1 || f.bit >= im.desc[im.u2i[f.site]].width)
+        if (f.site >= im.N || f.stuck > RIROS_FAULT_FLIP || f.bit >= im.desc[im.u2i[f.site]].width)
             return set_err(RIROS_EINVAL, "invalid fault " + std::to_string(i));
     }
     DevBuf<riros_fault> df;
@@ -634,7 +635,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         const riros::Image& im = designs[i]->img;
         for (uint32_t j = 0; j < F[i]; ++j) {
             const riros_fault& f = faults[i][j];
-            if (f.site >= im.N || f.stuck > 1 || f.bit >= im.desc[im.u2i[f.site]].width)
+            if (f.site >= im.N || f.stuck > RIROS_FAULT_FLIP || f.bit >= im.desc[im.u2i[f.site]].width)
                 return set_err(RIROS_EINVAL, "design " + std::to_string(i) + " fault " + std::to_string(j) + " invalid");
         }
         total += F[i];
@@ -644,7 +645,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         Tmax = std::max(Tmax, goldens[i]->T);
     }
     if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
-    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax) * sizeof(uint32_t);
+    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax, riros::kRecCacheBig) * sizeof(uint32_t);
     if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "largest design too large for the structural path's LDS bitmap");
     DeviceGuard guard(dev);
     riros_batch b = new (std::nothrow) riros_batch_s();
@@ -688,8 +689,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     riros::Slot* d_slots = nullptr;
     uint64_t* d_regs = nullptr;
     uint64_t* d_stamp = nullptr;
-    int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 12;
-    wpc = std::min(std::min(wpc, (int)std::max<size_t>(1, (160 * 1024) / lds)), 32);
+    // Grids are clamped to what is resident at once when the graph is built.
+    const int wpc = std::min(opts->waves_per_cu > 0 ? opts->waves_per_cu : 12, 32);
     const uint32_t blocks = (uint32_t)designs[0]->num_cu * (uint32_t)wpc;
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };

@@ -167,7 +167,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     // One design: uniform for the whole wave.  Batched: per lane, per fault.
     LaneDesign d = lane_design(src.d, src.g);
 
-    uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, t = 0, det = RIROS_UNDETECTED;
+    uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, ft0 = 0, t = 0, det = RIROS_UNDETECTED;
     uint64_t ev = 0;
     bool in_cycle = false;
     uint64_t exw = 0;
@@ -206,6 +206,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     site = d.u2i[f.site];
                     fbit = f.bit;
                     fval = f.stuck;
+                    ft0 = f.t0;
                     srec = d.rec[site];
                     bprow = (size_t)(d.bp_off[site] + fbit) * d.TW;
                     const uint32_t nf = srec.fo1 - srec.fo0;
@@ -244,10 +245,15 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         bool evaluated = false;
         if (!in_cycle) {
             if (rcur.n == 0) {
-                // Skip to the next cycle in which the site is excited.
+                // Skip to the next cycle in which the site is excited (a flip:
+                // its own cycle only).
                 bool found = false;
                 const uint32_t T = d.T;
-                while (t < T) {
+                if (fval == RIROS_FAULT_FLIP) {
+                    found = t <= ft0 && ft0 < T;
+                    t = ft0;
+                }
+                while (fval != RIROS_FAULT_FLIP && t < T) {
                     const uint32_t wb = t >> 6;
                     if (wb != ewb) {
                         uint64_t w = d.Bp[bprow + wb];
@@ -309,7 +315,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     if (k < ar) xs[k] ^= div.find(ins[k], din);
                 delta = apply_opw(r.op, r.width, r.b, r.c, xs[0], xs[1], xs[2]) ^ gv;
             }
-            if (n == site) delta = force_bit(gv ^ delta, fbit, fval) ^ gv;
+            if (n == site) delta = apply_fault(gv ^ delta, fbit, fval, t, ft0) ^ gv;
             const bool dout = delta != 0;
             if (din || dout) ev++;
             if (dout) on_divergent(n, delta, r, p0, p1, p2, p3);
@@ -361,9 +367,9 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
         const uint32_t k = src.did[fi];
         const DevDesign dd = src.td[k];
         const GoldenView gg = src.tg[k];
-        wave_sim_fault(dd, gg.Gn, gg.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(dd, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     } else {
-        wave_sim_fault(src.d, src.g.Gn, src.g.T, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(src.d, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     }
     if (threadIdx.x == 0) {
         detect_out[fi] = det;
@@ -463,7 +469,7 @@ __global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
-        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, kRecCacheSmall);
         wave_lds_clear(s, mx.N, mx.L, mx.R);
         __syncthreads();
         Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
                                                uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, kRecCacheBig);
     wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
@@ -621,6 +627,17 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     return l;
 }
 
+// LDS of launch A with structural work (small record cache: its LDS also
+// bounds the light lanes) and of launch B (structural work only).
+static size_t lds_bytes_a(const MaxShape& mx)
+{
+    return wave_lds_words(mx.N, mx.L, mx.R, kRecCacheSmall) * sizeof(uint32_t);
+}
+static size_t lds_bytes_b(const MaxShape& mx)
+{
+    return wave_lds_words(mx.N, mx.L, mx.R, kRecCacheBig) * sizeof(uint32_t);
+}
+
 // Persistent launches never exceed what can be resident at once (phase 3
 // waits for every wavefront of its launch to finish light work).
 static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want)
@@ -647,7 +664,7 @@ static const void* kernel_a_any(int cap, bool batch, bool structural)
 
 static uint32_t twod_blocks_a(int cap, bool batch, bool structural, const MaxShape& mx, uint32_t want)
 {
-    const size_t lds = structural ? wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t) : 0;
+    const size_t lds = structural ? lds_bytes_a(mx) : 0;
     const void* k = kernel_a_any(cap, batch, structural);
     if (structural && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return std::min(want, kTicketPad);
@@ -660,9 +677,9 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
                                 int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
                                 uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
-    const size_t lds = wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
+    const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
     hipError_t e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+                                       (int)ldsb);
     if (e != hipSuccess) return e;
     const bool structural = heavy || unified;
     const uint32_t ba = twod_blocks_a(C, BATCH, structural, mx, blocks);
@@ -675,7 +692,8 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
         hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ba), dim3(64), 0, s, src, mx, faults, F, order, ctr,
                            esc, drop, ws, rate_num, 0, detect, events);
     }
-    hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(blocks), dim3(64), lds, s, src, mx, faults, ctr, esc, drop, ws, span,
+    const uint32_t bb = resident_blocks((const void*)k_twod_b<BATCH>, ldsb, blocks);
+    hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(bb), dim3(64), ldsb, s, src, mx, faults, ctr, esc, drop, ws, span,
                        detect, events);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -769,17 +787,19 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
 
 hipError_t prepare_twod_batch(BatchPlan& b)
 {
-    const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
+    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
     hipError_t e = hipSuccess;
-    auto attr = [&](const void* f) {
+    auto attr = [&](const void* f, size_t lds) {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    attr((const void*)k_twod_a<4, true, true>);
-    attr((const void*)k_twod_a<8, true, true>);
-    attr((const void*)k_twod_a<16, true, true>);
-    attr((const void*)k_twod_b<true>);
-    if (e == hipSuccess)
-        b.blocks_a = twod_blocks_a(b.light_cap, true, b.heavy || b.unified, MaxShape{b.Nmax, b.Lmax, b.Rmax}, b.blocks);
+    attr((const void*)k_twod_a<4, true, true>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<8, true, true>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<16, true, true>, lds_bytes_a(mx));
+    attr((const void*)k_twod_b<true>, lds_bytes_b(mx));
+    if (e == hipSuccess) {
+        b.blocks_a = twod_blocks_a(b.light_cap, true, b.heavy || b.unified, mx, b.blocks);
+        b.blocks_b = resident_blocks((const void*)k_twod_b<true>, lds_bytes_b(mx), b.blocks);
+    }
     return e;
 }
 
@@ -810,7 +830,7 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     hipLaunchKernelGGL(k_reset_run_counters, dim3(1), dim3(64), 0, s, ctr);
     DesignSrc src{b.td_host0, b.tg_host0, b.td, b.tg, b.did};
     const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
-    const size_t lds = wave_lds_words(b.Nmax, b.Lmax, b.Rmax) * sizeof(uint32_t);
+    const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
 #define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(64), L, s, src, mx, b.faults, b.F, b.order, \
                        ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events)
@@ -831,7 +851,7 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
         }
     }
 #undef RIROS_LAUNCH_A
-    hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks), dim3(64), lds, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
+    hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks_b), dim3(64), ldsb, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
                        b.span, b.detect, b.events);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -63,6 +63,7 @@ struct BatchPlan {
     uint32_t rate_num = 0;
     uint32_t blocks = 0;      // launch B (and workspace) grid
     uint32_t blocks_a = 0;    // launch A grid (at most what is resident at once)
+    uint32_t blocks_b = 0;    // launch B grid (likewise)
     uint64_t span = 0;        // an upper bound of the stamps one block can use
     PlainWorkspace ws{};
     uint32_t* detect = nullptr;

@@ -10,33 +10,49 @@ namespace riros {
 
 constexpr uint32_t kListCap = 2048;
 
-// LDS of one wave: sched[N/32] nodes to evaluate this cycle; lvlm[L/32]
-// levels holding scheduled nodes; rcur/rnext[R/32] registers whose state
-// diverges in this / the next cycle; list[kListCap] compacted node ids; flags.
+// LDS of one wave: crec[K][8] / ctag[K] a direct-mapped cache of node records
+// (a long-lived fault evaluates much the same nodes every cycle, so most
+// records come from LDS instead of a global round trip); sched[N/32] nodes to
+// evaluate this cycle; lvlm[L/32] levels holding scheduled nodes;
+// rcur/rnext[R/32] registers whose state diverges in this / the next cycle;
+// list[kListCap] compacted node ids; flags; lvloff[L+1] the design's level
+// offsets (read once per fault, not per level).
+constexpr uint32_t kRecCacheBig = 256;    // launches that only run the structural path
+constexpr uint32_t kRecCacheSmall = 32;   // launches whose LDS also limits light lanes
+
 struct WaveLds {
+    uint32_t* crec;
+    uint32_t* ctag;
+    uint32_t cmask;
     uint32_t* sched;
     uint32_t* lvlm;
     uint32_t* rcur;
     uint32_t* rnext;
     uint32_t* list;
     uint32_t* flags;
+    uint32_t* lvloff;
 };
 
-__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R)
+// K: record-cache entries, a power of two.
+__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R, uint32_t K)
 {
-    return (size_t)(N + 31) / 32 + (L + 31) / 32 + 2 * ((R + 31) / 32) + kListCap + 4;
+    return (size_t)9 * K + (N + 31) / 32 + (L + 31) / 32 + 2 * ((R + 31) / 32) + kListCap + 4 + (L + 1);
 }
 
-__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R)
+__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R, uint32_t K)
 {
     const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
     WaveLds s;
-    s.sched = base;
+    s.crec = base;   // 16-byte aligned: records are read and written 16 bytes at a time
+    s.ctag = s.crec + 8 * K;
+    s.cmask = K - 1;
+    s.sched = s.ctag + K;
     s.lvlm = s.sched + W;
     s.rcur = s.lvlm + WL;
     s.rnext = s.rcur + WR;
     s.list = s.rnext + WR;
     s.flags = s.list + kListCap;
+    s.lvloff = s.flags + 4;
     return s;
 }
 
@@ -54,28 +70,26 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 // ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform) and the
 // event count (wave total).  Must be called by all 64 lanes of a one-wave
 // workgroup (it uses __syncthreads as the wave's LDS fence).
-__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gn, uint32_t T,
+__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gn,
+                                      const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                       const riros_fault f, int drop, const WaveLds& s,
                                       Slot* __restrict__ slots, uint64_t* __restrict__ regs,
                                       uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
 {
-    const uint32_t N = d.N, R = d.R;
+    const uint32_t R = d.R;
     const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t site = d.u2i[f.site];
     const uint32_t site_lvl = d.level[site];
-    const uint32_t fbit = f.bit, fval = f.stuck;
+    const uint32_t fbit = f.bit, fval = f.stuck, ft0 = f.t0;
+    const uint64_t* __restrict__ srow = Bp + (size_t)(d.bp_off[site] + fbit) * TW;   // the site bit, 64 cycles a word
     for (uint32_t i = lane; i < WR; i += 64) s.rnext[i] = 0;
+    for (uint32_t i = lane; i <= d.L; i += 64) s.lvloff[i] = d.lvl_off[i];
+    for (uint32_t i = lane; i <= s.cmask; i += 64) s.ctag[i] = 0xFFFFFFFFu;   // records of this fault's design
     uint32_t ev = 0;
     uint32_t det = RIROS_UNDETECTED;
     __syncthreads();
     for (uint32_t t = 0; t < T; ++t) {
-        const uint64_t stamp = stamp0 + t + 1;
-        // Node-major golden values: a node evaluated in consecutive cycles
-        // reads one cache line per eight cycles.
-        auto gold = [&](uint32_t n) { return Gn[(size_t)n * T + t]; };
-        const uint64_t* rst = regs + (size_t)(t & 1) * R;
-        uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
         // Cycle start: registers whose D diverged last cycle are scheduled.
         uint32_t any = 0;
         for (uint32_t i = lane; i < WR; i += 64) {
@@ -86,6 +100,38 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             any |= m;
         }
         const bool anyreg = __ballot(any != 0) != 0;
+        if (!anyreg) {
+            // No divergent state: the machine equals the golden one until the
+            // site is next excited (its golden bit differs from the stuck
+            // value; a flip, only in its cycle), so jump there; no event and
+            // no detection in between.
+            bool found = false;
+            if (fval == RIROS_FAULT_FLIP) {
+                found = t <= ft0 && ft0 < T;
+                t = ft0;
+            }
+            while (fval != RIROS_FAULT_FLIP && t < T) {
+                const uint32_t wb = t >> 6;
+                uint64_t w = srow[wb];
+                if (fval) w = ~w;
+                const uint32_t valid = T - (wb << 6);
+                if (valid < 64) w &= (1ull << valid) - 1ull;
+                const uint64_t m = w >> (t & 63);
+                if (m) {
+                    t += (uint32_t)__builtin_ctzll(m);
+                    found = true;
+                    break;
+                }
+                t = (wb + 1) << 6;
+            }
+            if (!found) break;
+        }
+        const uint64_t stamp = stamp0 + t + 1;
+        // Node-major golden values: a node evaluated in consecutive cycles
+        // reads one cache line per eight cycles.
+        auto gold = [&](uint32_t n) { return Gn[(size_t)n * T + t]; };
+        const uint64_t* rst = regs + (size_t)(t & 1) * R;
+        uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
         if (lane == 0) s.flags[0] = 0;
         __syncthreads();
         if (lane == 0) {
@@ -111,7 +157,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             if (lv < 0) break;
             __syncthreads();
             if (lane == 0) s.lvlm[lv >> 5] &= ~(1u << (lv & 31));
-            const uint32_t lo = d.lvl_off[lv], hi = d.lvl_off[lv + 1];
+            const uint32_t lo = s.lvloff[lv], hi = s.lvloff[lv + 1];
             const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5;
             for (uint32_t wb = w0; wb <= w1; wb += 64) {
                 const uint32_t w = wb + lane;
@@ -136,9 +182,32 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 __syncthreads();
                 for (uint32_t i = lane; i < total; i += 64) {
                     const uint32_t n = s.list[i];
-                    // Record (descriptor + fan-out ranges) and the node's golden value in one round trip,
-                    // then operands and the first fan-out entries in a second.
-                    const NodeRec x = d.rec[n];
+                    // Record (descriptor + fan-out ranges) from the LDS cache when present, then the
+                    // node's golden value, operands and first fan-out entries in one round trip.
+                    const uint32_t cs = n & s.cmask;
+                    // Every lane reads its line before any lane refills one, so a hit never sees a
+                    // record that a colliding lane writes in this same pass.  The reads are volatile:
+                    // otherwise the compiler may sink them into the hit branch and run that branch
+                    // after the refill branch.
+                    volatile uint32_t* const vt = s.ctag + cs;
+                    volatile uint64_t* const vr = (volatile uint64_t*)(s.crec + 8 * cs);
+                    const bool hit = *vt == n;
+                    uint64_t cw[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) cw[k] = vr[k];
+                    NodeRec x;
+                    if (hit) {
+                        __builtin_memcpy(&x, cw, sizeof x);
+                    } else {
+                        x = d.rec[n];
+                        // Lanes that collide on a line: the one whose tag write lands fills it.
+                        *vt = n;
+                        if (*vt == n) {
+                            __builtin_memcpy(cw, &x, sizeof x);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) vr[k] = cw[k];
+                        }
+                    }
                     const uint64_t gv = gold(n);
                     const uint32_t nf = x.fo1 - x.fo0;
                     const uint64_t pk0 = nf > 0 ? d.fo_pk[x.fo0] : 0;
@@ -166,7 +235,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         }
                         v = apply_opw(x.op, x.width, x.b, x.c, xs[0], xs[1], xs[2]);
                     }
-                    if (n == site) v = force_bit(v, fbit, fval);
+                    if (n == site) v = apply_fault(v, fbit, fval, t, ft0);
                     const bool dout = v != gv;
                     ev += (din || dout) ? 1u : 0u;
                     if (dout) {

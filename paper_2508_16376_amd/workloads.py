@@ -41,7 +41,9 @@ ARITY = {CONST: 0, PI: 0, REG: 1, ADD: 2, SUB: 2, AND: 2, OR: 2, XOR: 2, NOT: 1,
 NODE_DTYPE = np.dtype([("op", "u1"), ("width", "u1"), ("pad", "<u2"),
                        ("in0", "<u4"), ("in1", "<u4"), ("in2", "<u4"),
                        ("param", "<u8")])
-FAULT_DTYPE = np.dtype([("site", "<u4"), ("bit", "u1"), ("stuck", "u1"), ("pad", "<u2")])
+# stuck: 0 or 1 for a stuck-at fault; FLIP for a single bit flip in cycle t0.
+FAULT_DTYPE = np.dtype([("site", "<u4"), ("bit", "u1"), ("stuck", "u1"), ("t0", "<u2")])
+FLIP = 2
 assert NODE_DTYPE.itemsize == 24 and FAULT_DTYPE.itemsize == 8
 
 UNDETECTED = 0xFFFFFFFF
@@ -572,6 +574,24 @@ def mlp_init_weights(seed: int) -> np.ndarray:
         else:
             parts.append(np.zeros(n))
     return np.concatenate(parts).astype(np.float32)
+
+
+def gen_flip_faults(seed: int, d: Design, F: int, T: int) -> np.ndarray:
+    """F single bit flips: site bits uniform over operator and register bits
+    (with replacement), flip cycles uniform in [0, min(T, 65536))."""
+    sites, w = fault_universe(d)
+    cum = np.concatenate([[0], np.cumsum(w)])
+    U = int(cum[-1])
+    st = Stream(sub_seed(seed, 4))
+    u = (st.many(F) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    idx = np.minimum((u * U).astype(np.int64), U - 1)
+    k = np.searchsorted(cum, idx, side="right") - 1
+    out = np.zeros(F, dtype=FAULT_DTYPE)
+    out["site"] = sites[k]
+    out["bit"] = idx - cum[k]
+    out["stuck"] = FLIP
+    out["t0"] = (st.many(F) % np.uint64(min(T, 65536))).astype(np.uint16)
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -146,7 +146,8 @@ def topo_order(nodes) -> list[int]:
 def simulate(design, stim_seqs: np.ndarray, fault=None):
     """Gate-level simulation of S independent stimulus sequences.
 
-    stim_seqs: uint64[S][T][num_pi].  fault: None or (site, bit, stuck).
+    stim_seqs: uint64[S][T][num_pi].  fault: None, (site, bit, stuck) for a
+    stuck-at gate, or (site, bit, 2, t0) for a bit inverted in cycle t0 only.
     Returns node values uint64[S][T][N] (bit-assembled for comparison only).
     """
     nodes = design.nodes
@@ -176,7 +177,11 @@ def simulate(design, stim_seqs: np.ndarray, fault=None):
                                int(nodes["param"][n]), S)
             if fault is not None and n == fault[0]:
                 bits = list(bits)
-                bits[fault[1]] = np.full(S, bool(fault[2]))
+                if fault[2] == 2:
+                    if t == fault[3]:
+                        bits[fault[1]] = ~bits[fault[1]]
+                else:
+                    bits[fault[1]] = np.full(S, bool(fault[2]))
             val[n] = bits
         for n in range(N):
             out[:, t, n] = bits_to_word(val[n])

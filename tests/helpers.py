@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2508_16376_amd.workloads import NODE_DTYPE, FAULT_DTYPE, PI, REG, CONST, Design
+from paper_2508_16376_amd.workloads import NODE_DTYPE, FAULT_DTYPE, FLIP, PI, REG, CONST, Design
 
 
 class Builder:
@@ -40,10 +40,15 @@ class Builder:
 
 
 def faults(rows):
+    """Rows (site, bit, stuck) or (site, bit, FLIP, t0)."""
     out = np.zeros(len(rows), dtype=FAULT_DTYPE)
-    for i, (s, b, v) in enumerate(rows):
-        out[i] = (s, b, v, 0)
+    for i, r in enumerate(rows):
+        out[i] = (r[0], r[1], r[2], r[3] if len(r) > 3 else 0)
     return out
+
+
+def fault_tuple(f):
+    return (int(f["site"]), int(f["bit"]), int(f["stuck"]), int(f["t0"]))
 
 
 def all_faults(design, sites=None):
@@ -54,6 +59,17 @@ def all_faults(design, sites=None):
         for b in range(int(design.nodes["width"][n])):
             rows.append((n, b, 0))
             rows.append((n, b, 1))
+    return faults(rows)
+
+
+def all_flip_faults(design, T, sites=None):
+    """A bit flip on every bit of the given sites (default: every node) in every cycle t0 < T."""
+    rows = []
+    sites = range(design.num_nodes) if sites is None else sites
+    for n in sites:
+        for b in range(int(design.nodes["width"][n])):
+            for t0 in range(T):
+                rows.append((n, b, FLIP, t0))
     return faults(rows)
 
 

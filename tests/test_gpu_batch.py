@@ -89,3 +89,18 @@ def test_full_size_campaign_sampled():
         assert cov["total"] == w.faults.size
         assert cov["detected"] == int((det != riros.UNDETECTED).sum())
         assert ((det < w.T) | (det == riros.UNDETECTED)).all()
+
+
+def test_campaign_with_flips():
+    """Stuck-at faults and bit flips mixed in one campaign, on two replays."""
+    ws = W.campaign(seed=515151, n=5, nodes=(300, 3000), faults=(200, 2000), cycles=(50, 300))
+    fls = [np.concatenate([w.faults, W.gen_flip_faults(600 + i, w.design, 500, w.T)]) for i, w in enumerate(ws)]
+    refs = [oracle.fault_sim(w.design, w.stimulus, w.T, fl) for w, fl in zip(ws, fls)]
+    ds, gs = _load(ws)
+    b = riros.Batch(ds, gs, fls, monitor_rate=1.0, unified=1)
+    for _ in range(2):
+        b.launch()
+        for i in range(len(ws)):
+            det, ev, _ = b.read(i)
+            np.testing.assert_array_equal(det, refs[i][0])
+            np.testing.assert_array_equal(ev, refs[i][1])

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import Builder, all_faults, faults
+from helpers import Builder, all_faults, all_flip_faults, faults
 from paper_2508_16376_amd import riros
 from paper_2508_16376_amd import workloads as W
 
@@ -274,3 +274,45 @@ def test_two_d_device_io_with_priority(small):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(det_dev.cpu().numpy().view(np.uint32), det)
     np.testing.assert_array_equal(ev_dev.cpu().numpy().view(np.uint64), ev)
+
+
+# ---------------------------------------------------------------------------
+# Bit flips (transient faults): the same paths, a different faulty-value rule
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("drop", [True, False])
+def test_flips_tiny_every_site_bit_and_cycle_window(tiny, mode, drop):
+    """A flip on every bit of every node, in cycles 0, 1, 63, 64 and the last."""
+    w = tiny
+    fl = all_flip_faults(w.design, 1)
+    rows = []
+    for t0 in (0, 1, 63, 64, w.T - 1, w.T):
+        f = fl.copy()
+        f["t0"] = t0
+        rows.append(f)
+    fl = np.concatenate(rows)
+    _check(w.design, w.stimulus, w.T, fl, mode, drop, variant=0)
+
+
+@pytest.mark.parametrize("kw", [{"mode": riros.MODE_PLAIN}, {"mode": riros.MODE_TWO_D},
+                                {"mode": riros.MODE_TWO_D, "monitor_rate": 1.0, "unified": 1},
+                                {"mode": riros.MODE_TWO_D, "light_cap": 4, "monitor_rate": 0.5}])
+def test_flips_and_stuck_mixed_small(small, kw):
+    w = small
+    fl = np.concatenate([w.faults[:2000], W.gen_flip_faults(17, w.design, 3000, w.T + 30)])
+    perm = np.argsort(W.counter_values(18, 0, fl.size))
+    fl = fl[perm]
+    kw = dict(kw)
+    mode = kw.pop("mode")
+    for drop in (True, False):
+        _check(w.design, w.stimulus, w.T, fl, mode, drop, **kw)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_flips_medium_full_size(mode):
+    """50,000 flips on the medium design, every one compared with the oracle."""
+    w = W.medium()
+    fl = W.gen_flip_faults(19, w.design, 50000, w.T)
+    _check(w.design, w.stimulus, w.T, fl, mode, True, unified=1 if mode == riros.MODE_TWO_D else 0,
+           monitor_rate=2.0 if mode == riros.MODE_TWO_D else 0.0)

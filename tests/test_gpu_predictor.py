@@ -36,9 +36,10 @@ def _batch(seed, B):
 def test_features_match_reference(small):
     d = riros.Design(small.design)
     g = riros.Golden(d, small.stimulus, small.T)
-    got = riros.features(d, g, small.faults)
+    fl = np.concatenate([small.faults, W.gen_flip_faults(5, small.design, 500, small.T + 20)])
+    got = riros.features(d, g, fl)
     G = oracle.golden(small.design, small.stimulus, small.T)
-    ref = FT.features(small.design, G, small.faults)
+    ref = FT.features(small.design, G, fl)
     np.testing.assert_allclose(got, ref, rtol=2e-6, atol=1e-6)
 
 

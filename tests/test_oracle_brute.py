@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from bitblast import simulate
-from helpers import all_faults
+from helpers import all_faults, all_flip_faults, fault_tuple
 from paper_2508_16376_amd.workloads import ARITY, CONST, PI, REG, gen_layered
 
 UND = oracle.UNDETECTED
@@ -87,12 +87,12 @@ def test_brute_force_all_sequences(didx):
         chunk = (seqs_int >> np.uint64(bits_per_cycle * t)) & np.uint64(7)
         seqs[:, t, 0] = chunk & np.uint64(1)
         seqs[:, t, 1] = chunk >> np.uint64(1)
-    fl = all_faults(d)
+    # every stuck-at fault and every bit flip in every cycle
+    fl = np.concatenate([all_faults(d), all_flip_faults(d, T)])
     # sample sequences for the oracle loop, but compare every sequence for a few faults
     rng_idx = np.linspace(0, seqs.shape[0] - 1, 256).astype(np.int64)
     for drop in (True, False):
-        ref = [reference_counts(d, seqs[rng_idx], tuple(int(x) for x in (f["site"], f["bit"], f["stuck"])), drop)
-               for f in fl]
+        ref = [reference_counts(d, seqs[rng_idx], fault_tuple(f), drop) for f in fl]
         for j, s in enumerate(rng_idx):
             for variant in (0, 1):
                 det, ev = oracle.fault_sim(d, seqs[s], T, fl, drop=drop, variant=variant)
@@ -111,8 +111,7 @@ def test_brute_force_every_sequence_detect_only():
         chunk = (seqs_int >> np.uint64(3 * t)) & np.uint64(7)
         seqs[:, t, 0] = chunk & np.uint64(1)
         seqs[:, t, 1] = chunk >> np.uint64(1)
-    fl = all_faults(d)
-    ref = np.stack([reference_counts(d, seqs, (int(f["site"]), int(f["bit"]), int(f["stuck"])), True)[0]
-                    for f in fl], axis=1)             # [S][F]
+    fl = np.concatenate([all_faults(d), all_flip_faults(d, T)])
+    ref = np.stack([reference_counts(d, seqs, fault_tuple(f), True)[0] for f in fl], axis=1)   # [S][F]
     got = np.stack([oracle.fault_sim(d, seqs[s], T, fl, variant=1)[0] for s in range(seqs.shape[0])])
     np.testing.assert_array_equal(got.astype(np.int64), ref)

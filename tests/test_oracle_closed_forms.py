@@ -139,3 +139,59 @@ def test_combinational_exhaustive_first_distinguishing_vector():
             diff = (good[:, d.po] != bad[:, d.po]).any(axis=1)
             want = int(np.argmax(diff)) if diff.any() else UND
             assert det[i] == want, (variant, f)
+
+
+# ---------------------------------------------------------------------------
+# Bit flips (a single-event upset of a register, a transient on a wire)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("drop", [True, False])
+def test_counter_register_flip(variant, drop):
+    """Flipping bit k of the counter state in cycle t0: the output differs at
+    t0 and from then on (the state keeps a difference of 2^k modulo 2^n); with
+    dropping the events are the register and the adder it feeds, at t0."""
+    n, T = 8, 300
+    d, cnt, add, _ = counter(n)
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    rows = [(cnt, k, 2, t0) for k in range(n) for t0 in (0, 1, 37, T - 1, T, 5000)]
+    det, ev = oracle.fault_sim(d, stim, T, faults(rows), drop=drop, variant=variant)
+    for i, (_, k, _, t0) in enumerate(rows):
+        if t0 >= T:
+            assert det[i] == UND and ev[i] == 0
+            continue
+        assert det[i] == t0
+        assert ev[i] == (2 if drop else 2 * (T - t0)), (k, t0)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_counter_adder_flip(variant):
+    """A flip of the adder output in cycle t0 reaches the state, so the
+    register output differs from t0 + 1 on; the adder output itself at t0."""
+    n, T = 8, 300
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    for po_is_adder in (False, True):
+        d, cnt, add, _ = counter(n, po_is_adder)
+        rows = [(add, k, 2, t0) for k in range(n) for t0 in (0, 5, 100, T - 1)]
+        det, _ = oracle.fault_sim(d, stim, T, faults(rows), variant=variant)
+        for i, (_, k, _, t0) in enumerate(rows):
+            want = t0 if po_is_adder else (t0 + 1 if t0 + 1 < T else UND)
+            assert det[i] == want, (po_is_adder, k, t0)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_delay_line_flip(variant):
+    """A flip at stage j in cycle t0 arrives at the output L - j cycles later,
+    whatever the data: d = t0 + L - j when that is before T."""
+    L, w, T = 5, 4, 60
+    d, x, regs = delay_line(L, w)
+    stim = (counter_values(78, 0, T) & np.uint64(15))[:, None]
+    rows = [(regs[j], b, 2, t0) for j in range(L) for b in range(w) for t0 in (0, 3, 40, T - 2)]
+    rows += [(x, b, 2, t0) for b in range(w) for t0 in (0, 50, T - L)]
+    det, ev = oracle.fault_sim(d, stim, T, faults(rows), drop=False, variant=variant)
+    for i, (site, b, _, t0) in enumerate(rows):
+        j = regs.index(site) + 1 if site in regs else 0     # the input is stage 0
+        want = t0 + L - j
+        assert det[i] == (want if want < T else UND), (j, b, t0)
+        # one divergent node per cycle from t0 through the last stage reached
+        assert ev[i] == min(L - j, T - 1 - t0) + 1, (j, b, t0)

@@ -64,3 +64,18 @@ def test_chain_cones_levels_and_cap():
     assert FT.cone_size(d, chain[0], cu, ru) == FT.CONE_CAP  # 1501 reachable, capped
     lvl = FT.levels(d)
     assert lvl[chain[0]] == 1 and lvl[chain[-1]] == 1501 and lvl[r] == 0
+
+
+def test_flip_excitation_is_one_cycle():
+    from helpers import faults
+    b = Builder()
+    x = b.pi(4)
+    r = b.reg(4)
+    b.set_d(r, x)
+    d = b.design([r])
+    T = 50
+    stim = (np.arange(T, dtype=np.uint64) % np.uint64(16))[:, None]
+    G = oracle.golden(d, stim, T)
+    f = FT.features(d, G, faults([(r, 1, 2, 10), (r, 1, 2, T), (r, 1, 0, 0)]))
+    assert f[0, 5] == 1.0 / T and f[1, 5] == 0.0
+    assert f[0, 4] == f[2, 4]          # the toggle rate does not depend on the fault model

@@ -166,3 +166,25 @@ def test_thread_count_does_not_matter(small):
     b = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults, G=G, nthreads=7)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_flips_o0_equals_o1_and_bounds(small, tiny_run):
+    """Bit flips: O0 and O1 agree; nothing is detected before the flip cycle;
+    a flip at or after the last cycle changes nothing; drop never changes detect."""
+    for w, G in (tiny_run, small):
+        fl = W.gen_flip_faults(99, w.design, 600, w.T + 40)      # some flips land at or after T
+        for drop in (True, False):
+            d0, e0 = oracle.fault_sim(w.design, w.stimulus, w.T, fl, G=G, variant=0, drop=drop)
+            d1, e1 = oracle.fault_sim(w.design, w.stimulus, w.T, fl, G=G, variant=1, drop=drop)
+            np.testing.assert_array_equal(d0, d1)
+            np.testing.assert_array_equal(e0, e1)
+        t0 = fl["t0"].astype(np.int64)
+        late = t0 >= w.T
+        assert late.any() and (~late).any()
+        assert (d1[late] == UND).all() and (e1[late] == 0).all()
+        det = d1 != UND
+        assert (d1[det].astype(np.int64) >= t0[det]).all()
+        # every flip before T changes its site for one cycle: at least one event
+        assert (e1[~late] >= 1).all()
+        dd, _ = oracle.fault_sim(w.design, w.stimulus, w.T, fl, G=G, variant=1, drop=True)
+        np.testing.assert_array_equal(dd, d1)

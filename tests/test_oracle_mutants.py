@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from bitblast import simulate
-from helpers import Builder, all_faults, faults
+from helpers import Builder, all_faults, all_flip_faults, fault_tuple, faults
 from paper_2508_16376_amd.workloads import (ADD, AND, CONCAT, EQ, MUL, MUX, NE, NOT, OR, SHL, SHR,
                                             SLICE, SUB, ULT, XOR)
 from test_oracle_brute import reference_counts, tiny_designs
@@ -31,6 +31,8 @@ MUTANTS = {
     "o1_output_divergence_not_counted": ("if (div_in || div_out) ev++;", "if (div_in) ev++;"),
     "shr_is_shl": ("case O_SHR: r = k >= 64 ? 0 : (a >> k);", "case O_SHR: r = k >= 64 ? 0 : (a << k);"),
     "mul_is_add": ("case O_MUL: r = a * b;", "case O_MUL: r = a + b;"),
+    "flip_one_cycle_late": ("return t == f->t0 ? (v ^ bit) : v;", "return t == f->t0 + 1u ? (v ^ bit) : v;"),
+    "flip_is_permanent": ("return t == f->t0 ? (v ^ bit) : v;", "return t >= f->t0 ? (v ^ bit) : v;"),
     "reset_value_ignored": ("state[r] = d->nd[r].param & o_mask(d->nd[r].width);\n    }\n    for (uint32_t t = 0; t < T; ++t) {\n        const uint64_t* row = stim + (size_t)t * d->npi;",
                             "state[r] = 0;\n    }\n    for (uint32_t t = 0; t < T; ++t) {\n        const uint64_t* row = stim + (size_t)t * d->npi;"),
 }
@@ -61,9 +63,9 @@ def _brute_pass(lib) -> bool:
         seqs[:, t, 0] = chunk & np.uint64(1)
         seqs[:, t, 1] = chunk >> np.uint64(1)
     for d in tiny_designs():
-        fl = all_faults(d)
+        fl = np.concatenate([all_faults(d), all_flip_faults(d, T)])
         for drop in (True, False):
-            ref = [reference_counts(d, seqs, (int(f["site"]), int(f["bit"]), int(f["stuck"])), drop) for f in fl]
+            ref = [reference_counts(d, seqs, fault_tuple(f), drop) for f in fl]
             for j in range(seqs.shape[0]):
                 for variant in (0, 1):
                     det, ev = lib.fault_sim(d, seqs[j], T, fl, drop=drop, variant=variant)
