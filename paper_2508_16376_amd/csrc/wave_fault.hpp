@@ -13,21 +13,26 @@ constexpr uint32_t kListCap = 2048;
 // LDS of one wave: crec[K][8] / ctag[K] a direct-mapped cache of node records
 // (a long-lived fault evaluates much the same nodes every cycle, so most
 // records come from LDS instead of a global round trip); sched[N/32] nodes to
-// evaluate this cycle; lvlm[L/32] levels holding scheduled nodes;
-// rcur/rnext[R/32] registers whose state diverges in this / the next cycle;
+// evaluate this cycle, with ssum one bit per non-empty sched word (a sparse
+// frontier in a wide level is found without scanning the level's words);
+// lvlm[L/32] levels holding scheduled nodes; rcur/rnext[R/32] registers whose
+// state diverges in this / the next cycle, with summaries rcsum/rnsum;
 // list[kListCap] compacted node ids; flags; lvloff[L+1] the design's level
 // offsets (read once per fault, not per level).
-constexpr uint32_t kRecCacheBig = 256;    // launches that only run the structural path
-constexpr uint32_t kRecCacheSmall = 32;   // launches whose LDS also limits light lanes
+constexpr uint32_t kRecCacheBig = 256;    // launch B (only the structural path, few wavefronts)
+constexpr uint32_t kRecCacheSmall = 32;   // launches whose LDS bounds occupancy (plain, launch A)
 
 struct WaveLds {
     uint32_t* crec;
     uint32_t* ctag;
     uint32_t cmask;
     uint32_t* sched;
+    uint32_t* ssum;
     uint32_t* lvlm;
     uint32_t* rcur;
     uint32_t* rnext;
+    uint32_t* rcsum;
+    uint32_t* rnsum;
     uint32_t* list;
     uint32_t* flags;
     uint32_t* lvloff;
@@ -36,7 +41,9 @@ struct WaveLds {
 // K: record-cache entries, a power of two.
 __host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R, uint32_t K)
 {
-    return (size_t)9 * K + (N + 31) / 32 + (L + 31) / 32 + 2 * ((R + 31) / 32) + kListCap + 4 + (L + 1);
+    const size_t W = (N + 31) / 32, WR = (R + 31) / 32;
+    return (size_t)9 * K + W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + kListCap + 4 +
+           (L + 1);
 }
 
 __device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R, uint32_t K)
@@ -47,10 +54,13 @@ __device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L,
     s.ctag = s.crec + 8 * K;
     s.cmask = K - 1;
     s.sched = s.ctag + K;
-    s.lvlm = s.sched + W;
+    s.ssum = s.sched + W;
+    s.lvlm = s.ssum + (W + 31) / 32;
     s.rcur = s.lvlm + WL;
     s.rnext = s.rcur + WR;
-    s.list = s.rnext + WR;
+    s.rcsum = s.rnext + WR;
+    s.rnsum = s.rcsum + (WR + 31) / 32;
+    s.list = s.rnsum + (WR + 31) / 32;
     s.flags = s.list + kListCap;
     s.lvloff = s.flags + 4;
     return s;
@@ -60,9 +70,10 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 {
     const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t i = lane; i < W; i += 64) s.sched[i] = 0;
-    for (uint32_t i = lane; i < WL; i += 64) s.lvlm[i] = 0;
-    for (uint32_t i = lane; i < 2 * WR; i += 64) s.rcur[i] = 0;
+    // sched, ssum and lvlm are contiguous, and so are rcur, rnext, rcsum, rnsum
+    const uint32_t a = W + (W + 31) / 32 + WL, b = 2 * WR + 2 * ((WR + 31) / 32);
+    for (uint32_t i = lane; i < a; i += 64) s.sched[i] = 0;
+    for (uint32_t i = lane; i < b; i += 64) s.rcur[i] = 0;
 }
 
 // Simulate fault f from cycle 0 (drop: stop after the detect cycle).  slots
@@ -77,13 +88,20 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                                       uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
 {
     const uint32_t R = d.R;
-    const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32;
+    const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32, WRS = (WR + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t site = d.u2i[f.site];
     const uint32_t site_lvl = d.level[site];
     const uint32_t fbit = f.bit, fval = f.stuck, ft0 = f.t0;
     const uint64_t* __restrict__ srow = Bp + (size_t)(d.bp_off[site] + fbit) * TW;   // the site bit, 64 cycles a word
-    for (uint32_t i = lane; i < WR; i += 64) s.rnext[i] = 0;
+    // Register state left by the previous fault on this wave: clear the words
+    // the summaries point at.
+    for (uint32_t j = lane; j < WRS; j += 64) {
+        for (uint32_t m = s.rcsum[j]; m; m &= m - 1) s.rcur[j * 32 + __ffs(m) - 1] = 0;
+        for (uint32_t m = s.rnsum[j]; m; m &= m - 1) s.rnext[j * 32 + __ffs(m) - 1] = 0;
+        s.rcsum[j] = 0;
+        s.rnsum[j] = 0;
+    }
     for (uint32_t i = lane; i <= d.L; i += 64) s.lvloff[i] = d.lvl_off[i];
     for (uint32_t i = lane; i <= s.cmask; i += 64) s.ctag[i] = 0xFFFFFFFFu;   // records of this fault's design
     uint32_t ev = 0;
@@ -91,13 +109,23 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     __syncthreads();
     for (uint32_t t = 0; t < T; ++t) {
         // Cycle start: registers whose D diverged last cycle are scheduled.
+        // Lane j owns summary word j, hence register words 32j..32j+31 and
+        // the sched summary word j (registers have the lowest ids).
         uint32_t any = 0;
-        for (uint32_t i = lane; i < WR; i += 64) {
-            const uint32_t m = s.rnext[i];
-            s.rcur[i] = m;
-            s.rnext[i] = 0;
-            s.sched[i] |= m;
-            any |= m;
+        for (uint32_t j = lane; j < WRS; j += 64) {
+            for (uint32_t m = s.rcsum[j]; m; m &= m - 1) s.rcur[j * 32 + __ffs(m) - 1] = 0;
+            const uint32_t nm = s.rnsum[j];
+            for (uint32_t m = nm; m; m &= m - 1) {
+                const uint32_t i = j * 32 + __ffs(m) - 1;
+                const uint32_t v = s.rnext[i];
+                s.rcur[i] = v;
+                s.rnext[i] = 0;
+                s.sched[i] |= v;
+                any |= v;
+            }
+            s.rcsum[j] = nm;
+            s.rnsum[j] = 0;
+            s.ssum[j] |= nm;
         }
         const bool anyreg = __ballot(any != 0) != 0;
         if (!anyreg) {
@@ -136,6 +164,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         __syncthreads();
         if (lane == 0) {
             s.sched[site >> 5] |= 1u << (site & 31);
+            s.ssum[site >> 10] |= 1u << ((site >> 5) & 31);
             s.lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
             if (anyreg) s.lvlm[0] |= 1u;
         }
@@ -158,8 +187,27 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             __syncthreads();
             if (lane == 0) s.lvlm[lv >> 5] &= ~(1u << (lv & 31));
             const uint32_t lo = s.lvloff[lv], hi = s.lvloff[lv + 1];
-            const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5;
-            for (uint32_t wb = w0; wb <= w1; wb += 64) {
+            const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5, s1 = w1 >> 5;
+            uint32_t wb = w0;
+            for (;;) {
+                // Next non-empty sched word at or after wb, from the summary
+                // (64 summary words, 65,536 nodes, per probe).
+                uint32_t nw = 0xFFFFFFFFu;
+                for (uint32_t sb = wb >> 5; sb <= s1; sb += 64) {
+                    const uint32_t sw = sb + lane;
+                    uint32_t sm = sw <= s1 ? s.ssum[sw] : 0u;
+                    if (sw == (wb >> 5)) sm &= ~0u << (wb & 31);
+                    const uint64_t bal = __ballot(sm != 0);
+                    if (bal) {
+                        const int first = __ffsll((unsigned long long)bal) - 1;
+                        const uint32_t mw = __shfl(sm, first, 64);
+                        nw = (sb + (uint32_t)first) * 32 + (uint32_t)(__ffs(mw) - 1);
+                        break;
+                    }
+                }
+                if (nw > w1) break;
+                wb = nw;
+                // Words wb..wb+63 of this level: one per lane.
                 const uint32_t w = wb + lane;
                 uint32_t bits = 0;
                 if (w <= w1) {
@@ -168,8 +216,13 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     if (w == w1 && (hi & 31)) m &= (1u << (hi & 31)) - 1u;
                     const uint32_t word = s.sched[w];
                     bits = word & m;
-                    if (bits) s.sched[w] = word & ~m;
+                    if (bits) {
+                        s.sched[w] = word & ~m;
+                        if ((word & ~m) == 0) atomicAnd(&s.ssum[w >> 5], ~(1u << (w & 31)));
+                    }
                 }
+                wb += 64;
+                if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
                 const uint32_t cnt = __popc(bits);
                 const uint32_t incl = wave_incl_scan(cnt);
                 const uint32_t total = __shfl(incl, 63, 64);
@@ -248,12 +301,14 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                             const uint64_t pk = e == x.fo0 ? pk0 : (e == x.fo0 + 1 ? pk1 : d.fo_pk[e]);
                             const uint32_t c = (uint32_t)pk, lc = (uint32_t)(pk >> 32);
                             atomicOr(&s.sched[c >> 5], 1u << (c & 31));
+                            atomicOr(&s.ssum[c >> 10], 1u << ((c >> 5) & 31));
                             atomicOr(&s.lvlm[lc >> 5], 1u << (lc & 31));
                         }
                         for (uint32_t e = x.rfo0; e < x.rfo1; ++e) {
                             const uint32_t r = d.rfo[e];
                             rnx[r] = v;
                             atomicOr(&s.rnext[r >> 5], 1u << (r & 31));
+                            atomicOr(&s.rnsum[r >> 10], 1u << ((r >> 5) & 31));
                         }
                     }
                 }
