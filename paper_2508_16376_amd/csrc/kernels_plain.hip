@@ -105,7 +105,7 @@ hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t
 // ---------------------------------------------------------------------------
 size_t plain_lds_bytes(const DevDesign& d)
 {
-    return wave_lds_words(d.N, d.L, d.R, kRecCacheSmall) * sizeof(uint32_t);
+    return wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
 }
 
 __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gn,
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
                                                     uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R, kRecCacheSmall);
+    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
     wave_lds_clear(s, d.N, d.L, d.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;

@@ -645,7 +645,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         Tmax = std::max(Tmax, goldens[i]->T);
     }
     if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
-    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax, riros::kRecCacheBig) * sizeof(uint32_t);
+    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax) * sizeof(uint32_t);
     if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "largest design too large for the structural path's LDS bitmap");
     DeviceGuard guard(dev);
     riros_batch b = new (std::nothrow) riros_batch_s();

@@ -37,7 +37,7 @@ struct TwoDCounters {
     uint32_t n_heavy;                   // faults placed on the heavy queue up front
     alignas(128) uint32_t esc_count;    // faults handed from light lanes to the heavy path
     alignas(128) uint32_t esc_head;     // launch B: next handed-over fault to look at
-    uint32_t light_done;                // wavefronts of launch A that finished their light work
+    uint32_t inflight;                  // light faults taken by a lane and not yet finished or handed over
     uint32_t error;                     // unused (kept zero)
     alignas(128) uint32_t esc_take;     // phase-3 tickets (launch A)
 };
@@ -181,7 +181,13 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     DeltaSet<CR> rcur, rnxt;
     pend.n = div.n = rcur.n = rnxt.n = 0;
 
+    bool finished = false;   // this lane finished or handed over a fault in the last iteration
     for (;;) {
+        // Count the faults finished in the last iteration out of flight (one
+        // atomic per wave), after their hand-overs were performed.
+        const uint64_t finm = __ballot(finished);
+        if (finm && (int)lane == __ffsll((unsigned long long)finm) - 1) atomicSub(&ctr->inflight, (uint32_t)__popcll(finm));
+        finished = false;
         // Refill idle lanes from the light queue (one atomic per wave); only
         // the first `lanes` lanes take work, so that light faults spread over
         // every wavefront of the grid.
@@ -191,7 +197,16 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             const uint32_t k = (uint32_t)__popcll(needm);
             const int leader = __ffsll((unsigned long long)needm) - 1;
             uint32_t base = 0;
-            if ((int)lane == leader) base = atomicAdd(&ctr->light_head, k);
+            if ((int)lane == leader) {
+                // In flight before taken (the fence waits for the increment),
+                // so that a taken fault is always counted: phase 3 ends when
+                // the queue is empty and nothing is in flight.
+                atomicAdd(&ctr->inflight, k);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                base = atomicAdd(&ctr->light_head, k);
+                const uint32_t taken = base >= nlight ? 0u : min(k, nlight - base);
+                if (taken < k) atomicSub(&ctr->inflight, k - taken);
+            }
             base = __shfl(base, leader, 64);
             if (base + k >= nlight) exhausted = true;
             if (need) {
@@ -275,6 +290,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     detect_out[fi] = det;
                     if (events_out) events_out[fi] = ev;
                     fi = kNone;
+                    finished = true;
                     continue;
                 }
                 ev++;
@@ -332,6 +348,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             // would write back or invalidate the whole L2 on every access.
             __hip_atomic_store(&esc[slot], fi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             fi = kNone;
+            finished = true;
             continue;
         }
         if (in_cycle && pend.n == 0) {
@@ -349,6 +366,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 detect_out[fi] = det;
                 if (events_out) events_out[fi] = ev;
                 fi = kNone;
+                finished = true;
             }
         }
     }
@@ -377,11 +395,11 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
     }
 }
 
-// Phase 3: take handed-over faults while launch A runs.  The wavefront first
-// counts itself as done with light work, then takes a ticket: the ticket-th
-// handed-over fault is its next one.  It waits (polling its own entry, with
-// backoff) until that fault is published, and simulates it; or until every
-// wavefront of the launch is done with light work and the list ended before
+// Phase 3: take handed-over faults while launch A runs.  A wavefront whose
+// lanes have run out of light work takes a ticket: the ticket-th handed-over
+// fault is its next one.  It waits (polling its own entry, with backoff) until
+// that fault is published, and simulates it; or until light work is over (the
+// queue is empty and no lane holds a light fault) and the list ended before
 // its ticket (then it leaves); or until a bounded idle time has passed (then
 // it leaves its ticket, and launch B simulates the fault if it comes).  A
 // simulated entry is overwritten with kDone, which launch B skips.
@@ -397,14 +415,11 @@ constexpr uint32_t kIdleLimit = 1u << 18;
 
 template <bool BATCH>
 __device__ void drain_handover(const DesignSrc& src, const riros_fault* __restrict__ faults, uint32_t F,
-                               TwoDCounters* ctr, uint32_t* esc, int drop, const WaveLds& s, Slot* slots,
+                               uint32_t nlight, TwoDCounters* ctr, uint32_t* esc, int drop, const WaveLds& s, Slot* slots,
                                uint64_t* regs, uint64_t& stamp0, uint32_t* __restrict__ detect_out,
                                uint64_t* __restrict__ events_out)
 {
     const uint32_t lane = threadIdx.x & 63;
-    // This wavefront's hand-overs all returned their slots before this point,
-    // so they are performed before the increment below.
-    if (lane == 0) __hip_atomic_fetch_add(&ctr->light_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t idle = 0;
     for (;;) {
         uint32_t fi = kNone, ticket = 0;
@@ -423,13 +438,18 @@ __device__ void drain_handover(const DesignSrc& src, const riros_fault* __restri
                     fi = v;
                     break;
                 }
-                // light_done first: once it is complete, esc_count read after
-                // it is final (the fence only waits for the load).
-                const uint32_t done = __hip_atomic_load(&ctr->light_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // Light work is over when the queue is empty and no lane holds
+                // a light fault; then esc_count read after it is final.  (Each
+                // load completes before the next is issued: the fences only
+                // wait.)  This does not depend on every wavefront of the
+                // launch being resident.
+                const uint32_t lh = __hip_atomic_load(&ctr->light_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const uint32_t inf = __hip_atomic_load(&ctr->inflight, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 const uint32_t c = __hip_atomic_load(&ctr->esc_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (ticket < c) continue;   // reserved: the store follows at once
-                if (done >= gridDim.x) {
+                if (lh >= nlight && inf == 0) {
                     leave = true;
                     break;
                 }
@@ -469,7 +489,7 @@ __global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
-        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, kRecCacheSmall);
+        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
         wave_lds_clear(s, mx.N, mx.L, mx.R);
         __syncthreads();
         Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
@@ -492,7 +512,8 @@ __global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const
         light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
                               events_out, lanes, rate_num);
         if (unified)
-            drain_handover<BATCH>(src, faults, F, ctr, esc, drop, s, slots, regs, stamp0, detect_out, events_out);
+            drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
+                                  events_out);
     } else {
         const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
         light_phase<C, BATCH>(src, faults, F, order, ctr, esc, drop, detect_out, events_out, lanes, rate_num);
@@ -508,7 +529,7 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
                                                uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, kRecCacheBig);
+    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
     wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
@@ -565,7 +586,7 @@ __global__ void k_reset_run_counters(TwoDCounters* ctr)
         ctr->heavy_head = 0;
         ctr->esc_head = 0;
         ctr->error = 0;
-        ctr->light_done = 0;
+        ctr->inflight = 0;
         ctr->esc_take = 0;
     }
 }
@@ -627,19 +648,18 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     return l;
 }
 
-// LDS of launch A with structural work (small record cache: its LDS also
-// bounds the light lanes) and of launch B (structural work only).
+// LDS of the structural path (launch A with structural work, launch B).
 static size_t lds_bytes_a(const MaxShape& mx)
 {
-    return wave_lds_words(mx.N, mx.L, mx.R, kRecCacheSmall) * sizeof(uint32_t);
+    return wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
 }
 static size_t lds_bytes_b(const MaxShape& mx)
 {
-    return wave_lds_words(mx.N, mx.L, mx.R, kRecCacheBig) * sizeof(uint32_t);
+    return wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
 }
 
-// Persistent launches never exceed what can be resident at once (phase 3
-// waits for every wavefront of its launch to finish light work).
+// Persistent launches never exceed what can be resident at once: the lane
+// quota assumes every wavefront of the launch runs from the start.
 static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want)
 {
     int dev = 0, per_cu = 0, cus = 0;

@@ -10,22 +10,14 @@ namespace riros {
 
 constexpr uint32_t kListCap = 2048;
 
-// LDS of one wave: crec[K][8] / ctag[K] a direct-mapped cache of node records
-// (a long-lived fault evaluates much the same nodes every cycle, so most
-// records come from LDS instead of a global round trip); sched[N/32] nodes to
+// LDS of one wave: sched[N/32] nodes to
 // evaluate this cycle, with ssum one bit per non-empty sched word (a sparse
 // frontier in a wide level is found without scanning the level's words);
 // lvlm[L/32] levels holding scheduled nodes; rcur/rnext[R/32] registers whose
 // state diverges in this / the next cycle, with summaries rcsum/rnsum;
 // list[kListCap] compacted node ids; flags; lvloff[L+1] the design's level
 // offsets (read once per fault, not per level).
-constexpr uint32_t kRecCacheBig = 256;    // launch B (only the structural path, few wavefronts)
-constexpr uint32_t kRecCacheSmall = 32;   // launches whose LDS bounds occupancy (plain, launch A)
-
 struct WaveLds {
-    uint32_t* crec;
-    uint32_t* ctag;
-    uint32_t cmask;
     uint32_t* sched;
     uint32_t* ssum;
     uint32_t* lvlm;
@@ -38,22 +30,18 @@ struct WaveLds {
     uint32_t* lvloff;
 };
 
-// K: record-cache entries, a power of two.
-__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R, uint32_t K)
+__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R)
 {
     const size_t W = (N + 31) / 32, WR = (R + 31) / 32;
-    return (size_t)9 * K + W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + kListCap + 4 +
+    return W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + kListCap + 4 +
            (L + 1);
 }
 
-__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R, uint32_t K)
+__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R)
 {
     const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
     WaveLds s;
-    s.crec = base;   // 16-byte aligned: records are read and written 16 bytes at a time
-    s.ctag = s.crec + 8 * K;
-    s.cmask = K - 1;
-    s.sched = s.ctag + K;
+    s.sched = base;
     s.ssum = s.sched + W;
     s.lvlm = s.ssum + (W + 31) / 32;
     s.rcur = s.lvlm + WL;
@@ -103,7 +91,6 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         s.rnsum[j] = 0;
     }
     for (uint32_t i = lane; i <= d.L; i += 64) s.lvloff[i] = d.lvl_off[i];
-    for (uint32_t i = lane; i <= s.cmask; i += 64) s.ctag[i] = 0xFFFFFFFFu;   // records of this fault's design
     uint32_t ev = 0;
     uint32_t det = RIROS_UNDETECTED;
     __syncthreads();
@@ -235,32 +222,11 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 __syncthreads();
                 for (uint32_t i = lane; i < total; i += 64) {
                     const uint32_t n = s.list[i];
-                    // Record (descriptor + fan-out ranges) from the LDS cache when present, then the
-                    // node's golden value, operands and first fan-out entries in one round trip.
-                    const uint32_t cs = n & s.cmask;
-                    // Every lane reads its line before any lane refills one, so a hit never sees a
-                    // record that a colliding lane writes in this same pass.  The reads are volatile:
-                    // otherwise the compiler may sink them into the hit branch and run that branch
-                    // after the refill branch.
-                    volatile uint32_t* const vt = s.ctag + cs;
-                    volatile uint64_t* const vr = (volatile uint64_t*)(s.crec + 8 * cs);
-                    const bool hit = *vt == n;
-                    uint64_t cw[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) cw[k] = vr[k];
-                    NodeRec x;
-                    if (hit) {
-                        __builtin_memcpy(&x, cw, sizeof x);
-                    } else {
-                        x = d.rec[n];
-                        // Lanes that collide on a line: the one whose tag write lands fills it.
-                        *vt = n;
-                        if (*vt == n) {
-                            __builtin_memcpy(cw, &x, sizeof x);
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) vr[k] = cw[k];
-                        }
-                    }
+                    // Record (descriptor + fan-out ranges) in one round trip, then the node's golden
+                    // value, operands and first fan-out entries in a second.  (A per-wave LDS cache
+                    // of records and of the active set's golden and faulty values was measured
+                    // slower: the LDS it takes costs more occupancy than it saves latency.)
+                    const NodeRec x = d.rec[n];
                     const uint64_t gv = gold(n);
                     const uint32_t nf = x.fo1 - x.fo0;
                     const uint64_t pk0 = nf > 0 ? d.fo_pk[x.fo0] : 0;
