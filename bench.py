@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # words, one faulty-value write).
 BYTES_PER_FC = 8
 BYTES_PER_EVENT = 32
+NO_DROP_SAMPLE = 2000
 
 WORKLOADS = {
     "tiny": "tiny: 144-node DAG (120 operators, 16 registers), 128 cycles, 2,000 stuck-at faults",
@@ -243,8 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-predictor", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--no-drop-leg", choices=["auto", "on", "off"], default="auto",
-                    help="extra run without fault dropping (the paper's convention); auto: when F*T <= 2e9")
+    ap.add_argument("--no-drop-leg", choices=["on", "off"], default="on",
+                    help="extra run without fault dropping (the paper's convention) on a sample of the faults")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one copy of known size (for scaling the HBM byte counters)")
     args = ap.parse_args()
@@ -330,18 +331,26 @@ def main():
         all(np.array_equal(a, b) for a, b in zip(static["detect"], best["detect"]))
 
     # The paper keeps every fault for every cycle (no dropping): one extra run
-    # in that convention, reported as nominal F*T per second.
+    # in that convention on a seeded sample of the fault list (without
+    # dropping, a detected fault keeps its divergence for the rest of the run,
+    # which on the layered designs costs minutes for the whole list), reported
+    # as nominal F*T per second of kernel time.
     nodrop = None
-    FT = sum(w.faults.size * w.T for w in ws)
-    if args.no_drop_leg == "on" or (args.no_drop_leg == "auto" and FT <= 2e9):
-        if multi:
-            nd = job.run_batch(1, 1, autotune.batch_kwargs(params, allp), preds, drop=False)
-        else:
-            nd = job.run(riros.MODE_TWO_D, 1, 1, autotune.single_kwargs(params, preds), drop=False)
-        nodrop = {"nominal_fault_cycles_per_s": FT / nd["wall_s"], "fault_cycles": FT, "kernel_ms": nd["kernel_ms"],
-                  "events": nd["events"],
-                  "detect_identical": all(np.array_equal(a, b) for a, b in zip(nd["detect"], best["detect"]))}
-        log(f"[bench] no-drop: kernel {nd['kernel_ms']:.3f} ms, {nodrop['nominal_fault_cycles_per_s']:.4g} F*T/s")
+    if args.no_drop_leg != "off" and not multi:
+        w = ws[0]
+        n = min(w.faults.size, NO_DROP_SAMPLE)
+        idx = np.sort(np.argsort(W.counter_values(0xD0D0, 0, w.faults.size), kind="stable")[:n])
+        kw = autotune.single_kwargs(params, None if preds is None else preds[idx])
+        pr = None if preds is None else np.ascontiguousarray(preds[idx], np.float32)
+        for _ in range(2):   # the first run also loads code objects
+            ndet, nev, _ = riros.fault_sim(job.d, job.g, w.faults[idx], mode=riros.MODE_TWO_D, drop=False,
+                                           priority=pr, **kw)
+            nd_ms = riros.last_kernel_ms()
+        FT = n * w.T
+        nodrop = {"sample_faults": n, "nominal_fault_cycles_per_s": FT / (nd_ms * 1e-3), "fault_cycles": FT,
+                  "kernel_ms": nd_ms, "events": int(nev.sum()),
+                  "detect_identical": bool(np.array_equal(ndet, best["detect"][0][idx]))}
+        log(f"[bench] no-drop sample of {n}: kernel {nd_ms:.3f} ms, {nodrop['nominal_fault_cycles_per_s']:.4g} F*T/s")
 
     FC, E = best["fault_cycles"], best["events"]
     value = rate(best, args.steps)
