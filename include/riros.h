@@ -149,6 +149,14 @@ typedef struct {
     float monitor_rate;    /* TWO_D: a light fault averaging more than this many
                               events per cycle after its first 8 cycles moves to
                               the structural path (0 = never) */
+    int32_t struct_share;  /* TWO_D, when launch A has structural work (a heavy
+                              prefix or unified): wavefronts of launch A per
+                              structural workspace (the LDS and faulty-value
+                              slots of one wavefront), 1, 2 or 4; the first
+                              takes the structural work, the others run light
+                              faults only.  0 = the smallest that keeps
+                              waves_per_cu wavefronts resident despite the
+                              structural LDS of the design, else 4 */
     void* stream;
 } riros_sim_opts;
 

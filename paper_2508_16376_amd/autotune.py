@@ -4,7 +4,8 @@ Chooses, per design (or campaign) and fault population, the parameters that
 decide where work runs: whether idle wavefronts take handed-over faults
 during the light launch (the unified schedule), the events-per-cycle
 threshold of the light-lane monitor, the light-lane capacity, the number of
-resident wavefronts per compute unit, and (with a predictor) the
+resident wavefronts per compute unit, how many of them share one structural
+workspace, and (with a predictor) the
 predicted-load quantile above which faults start on the structural path.  The paper fixes its overload threshold
 by hand (Sec. V-A); here candidates are timed and the fastest kept, one
 parameter at a time (coordinate descent), with the result cached by design
@@ -29,9 +30,11 @@ SPACE = {
     "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
     "light_cap": [4, 8],
     "waves_per_cu": [8, 12, 16],
-    "heavy_quantile": [None, 0.999, 0.99],
+    "struct_share": [1, 2, 4],
+    "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
-DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "heavy_quantile": None}
+DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 0,
+           "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -45,7 +48,7 @@ def _opts(p, priority):
     if priority is not None and p["heavy_quantile"] is not None:
         theta = float(np.quantile(priority, p["heavy_quantile"]))
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
-            "unified": p.get("unified", 0), "theta": theta}
+            "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):
@@ -79,20 +82,27 @@ class Autotuner:
         best_t = measure(best)
         self.log.append({"params": dict(best), "ms": best_t})
         seen = {tuple(sorted(best.items(), key=lambda kv: kv[0]))}
-        for name, values in SPACE.items():
-            if name == "heavy_quantile" and not with_priority:
-                continue
-            for v in values:
-                cand = dict(best)
-                cand[name] = v
-                key = tuple(sorted(cand.items(), key=lambda kv: kv[0]))
-                if key in seen:
+        # Two passes at most: a parameter chosen early (say the monitor rate)
+        # may lose its worth once a later one moves (most faults starting on
+        # the structural path); the second pass only times unseen points.
+        for _ in range(2):
+            start = dict(best)
+            for name, values in SPACE.items():
+                if name == "heavy_quantile" and not with_priority:
                     continue
-                seen.add(key)
-                t = measure(cand)
-                self.log.append({"params": dict(cand), "ms": t})
-                if t < best_t:
-                    best, best_t = cand, t
+                for v in values:
+                    cand = dict(best)
+                    cand[name] = v
+                    key = tuple(sorted(cand.items(), key=lambda kv: kv[0]))
+                    if key in seen:
+                        continue
+                    seen.add(key)
+                    t = measure(cand)
+                    self.log.append({"params": dict(cand), "ms": t})
+                    if t < best_t:
+                        best, best_t = cand, t
+            if best == start:
+                break
         return best, best_t
 
     def tune_single(self, design_np, d, g, faults, priority=None, T=None):

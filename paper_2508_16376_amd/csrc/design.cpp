@@ -198,6 +198,14 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
         if (!fo[i].empty()) img.desc[i].flags |= DF_COMBFO;
         if (!rfo[i].empty()) img.desc[i].flags |= DF_REGFO;
     }
+    // Each table ends in kFanoutPad zero entries, so that a kernel may read
+    // the first kFanoutPad entries of any node's list without a bounds check
+    // (issuing them together with the operand loads) and use those in range.
+    for (uint32_t k = 0; k < kFanoutPad; ++k) {
+        img.fo.push_back(0);
+        img.fo_pk.push_back(0);
+        img.rfo.push_back(0);
+    }
     std::vector<uint8_t> seen(N, 0);
     img.po.clear();
     img.rec.assign(N, NodeRec{});

@@ -24,6 +24,9 @@ static_assert(sizeof(Desc) == 16, "descriptor layout");
 
 enum : uint8_t { DF_PO = 1, DF_REGFO = 2, DF_COMBFO = 4 };
 
+// Zero entries after the last fan-out entry of fo, fo_pk and rfo.
+constexpr uint32_t kFanoutPad = 4;
+
 // 32-byte node record for per-lane walks: the descriptor plus the node's
 // fan-out ranges, so one load gives everything needed to evaluate a node and
 // schedule its users.
@@ -44,6 +47,7 @@ struct Image {
     std::vector<uint32_t> fo_off, fo, fo_lvl;   // combinational users (deduplicated)
     std::vector<uint64_t> fo_pk;                // user id | level << 32
     std::vector<uint32_t> rfo_off, rfo;         // registers whose D is this node
+    // fo, fo_pk and rfo end in kFanoutPad zero entries (fo_lvl does not).
     std::vector<uint32_t> po;                   // internal ids, deduplicated
     std::vector<NodeRec> rec;                   // per internal node
     std::vector<uint32_t> bp_off;               // first bit-plane row of each node (prefix sum of widths)

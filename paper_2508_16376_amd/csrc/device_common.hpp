@@ -88,6 +88,18 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x)
     return x;
 }
 
+// Orders one wavefront's LDS accesses across its lanes (writes before the
+// call are seen by reads after it) without a workgroup barrier, so that one
+// wavefront of a larger workgroup can use it alone.  The workgroup-scope
+// fences wait for the wave's outstanding LDS operations; the wave barrier
+// keeps the compiler from moving memory operations across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ uint64_t make_u64(uint32_t lo, uint32_t hi)
 {
     return (uint64_t)lo | ((uint64_t)hi << 32);

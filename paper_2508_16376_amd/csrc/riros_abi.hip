@@ -28,6 +28,11 @@ int set_err(int code, const std::string& msg)
     return code;
 }
 
+bool valid_share(int32_t v)
+{
+    return v == 0 || v == 1 || v == 2 || v == 4;
+}
+
 int hip_err(hipError_t e, const char* what)
 {
     char buf[256];
@@ -321,9 +326,10 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
         return set_err(RIROS_EINVAL, "unknown mode");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
-        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
-        return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, or "
-                                     "light_cap not 0, 4, 8 or 16)");
+        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
+        !valid_share(opts->struct_share))
+        return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, "
+                                     "light_cap not 0, 4, 8 or 16, or struct_share not 0, 1, 2 or 4)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -414,6 +420,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.theta = opts->theta;
         p.light_cap = opts->light_cap;
         p.unified = opts->unified;
+        p.share = opts->struct_share;
         p.waves_per_cu = opts->waves_per_cu;
         p.num_cu = d->num_cu;
         std::string err;
@@ -622,7 +629,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (opts->mode != RIROS_MODE_TWO_D || opts->io_on_device)
         return set_err(RIROS_EINVAL, "campaigns run in RIROS_MODE_TWO_D with host-side inputs");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
-        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16))
+        (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
+        !valid_share(opts->struct_share))
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
@@ -743,6 +751,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (rc) return fail(rc, err);
     p.heavy = d_pr != nullptr && !(opts->theta > 3.0e38f);
     p.unified = opts->unified;
+    p.share = opts->struct_share;
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);
     if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign preparation: ") + hipGetErrorString(e));

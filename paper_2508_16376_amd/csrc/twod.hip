@@ -224,11 +224,10 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     ft0 = f.t0;
                     srec = d.rec[site];
                     bprow = (size_t)(d.bp_off[site] + fbit) * d.TW;
-                    const uint32_t nf = srec.fo1 - srec.fo0;
-                    sf0 = nf > 0 ? d.fo[srec.fo0] : 0;
-                    sf1 = nf > 1 ? d.fo[srec.fo0 + 1] : 0;
-                    sf2 = nf > 2 ? d.fo[srec.fo0 + 2] : 0;
-                    sf3 = nf > 3 ? d.fo[srec.fo0 + 3] : 0;
+                    sf0 = d.fo[srec.fo0];
+                    sf1 = d.fo[srec.fo0 + 1];
+                    sf2 = d.fo[srec.fo0 + 2];
+                    sf3 = d.fo[srec.fo0 + 3];
                     t = 0;
                     det = RIROS_UNDETECTED;
                     ev = 0;
@@ -306,30 +305,31 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         }
         if (!evaluated && !esc_now) {
             // Evaluate the lowest pending node (users always have larger ids).
+            // The record, then everything it points at in one round trip:
+            // unconditional loads combined with selects (an operand slot the
+            // operator does not read repeats the first operand, or the node
+            // itself; the fan-out table ends in padding), so no load waits
+            // for another.
             const uint32_t n = pend.pop_min();
             const NodeRec r = d.rec[n];
             const uint32_t T = d.T;
             const uint64_t gv = d.Gn[(size_t)n * T + t];
-            const uint32_t nf = r.fo1 - r.fo0;
-            const uint32_t p0 = nf > 0 ? d.fo[r.fo0] : 0;
-            const uint32_t p1 = nf > 1 ? d.fo[r.fo0 + 1] : 0;
-            const uint32_t p2 = nf > 2 ? d.fo[r.fo0 + 2] : 0;
-            const uint32_t p3 = nf > 3 ? d.fo[r.fo0 + 3] : 0;
+            const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
+            const int ar = comb ? dev_arity(r.op) : 0;
+            const uint32_t i0 = ar > 0 ? r.a : n;
+            const uint32_t i1 = ar > 1 ? r.b : i0;
+            const uint32_t i2 = ar > 2 ? r.c : i0;
+            uint64_t x0 = d.Gn[(size_t)i0 * T + t], x1 = d.Gn[(size_t)i1 * T + t], x2 = d.Gn[(size_t)i2 * T + t];
+            const uint32_t p0 = d.fo[r.fo0], p1 = d.fo[r.fo0 + 1], p2 = d.fo[r.fo0 + 2], p3 = d.fo[r.fo0 + 3];
             uint64_t delta = 0;
             bool din = false;
             if (r.op == RIROS_OP_REG) {
                 delta = rcur.find(n, din);
-            } else if (r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST) {
-                const int ar = dev_arity(r.op);
-                const uint32_t ins[3] = {r.a, r.b, r.c};
-                uint64_t xs[3] = {0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    if (k < ar) xs[k] = d.Gn[(size_t)ins[k] * T + t];
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    if (k < ar) xs[k] ^= div.find(ins[k], din);
-                delta = apply_opw(r.op, r.width, r.b, r.c, xs[0], xs[1], xs[2]) ^ gv;
+            } else if (comb) {
+                x0 ^= div.find(i0, din);
+                if (ar > 1) x1 ^= div.find(i1, din);
+                if (ar > 2) x2 ^= div.find(i2, din);
+                delta = apply_opw(r.op, r.width, r.b, r.c, x0, x1, x2) ^ gv;
             }
             if (n == site) delta = apply_fault(gv ^ delta, fbit, fval, t, ft0) ^ gv;
             const bool dout = delta != 0;
@@ -404,10 +404,10 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
 // it leaves its ticket, and launch B simulates the fault if it comes).  A
 // simulated entry is overwritten with kDone, which launch B skips.
 constexpr uint32_t kDone = 0xFFFFFFFEu;
-// Tickets never exceed the hand-overs plus one per wavefront of launch A
-// (each holds at most one unfilled ticket), and launch A never has more than
-// kTicketPad wavefronts: the list has F + kTicketPad entries, all kNone at the
-// start of a run.
+// Tickets never exceed the hand-overs plus one per workgroup of launch A
+// (only its first wavefront takes tickets, and holds at most one unfilled
+// ticket), and launch A never has more than kTicketPad workgroups: the list
+// has F + kTicketPad entries, all kNone at the start of a run.
 constexpr uint32_t kTicketPad = 8192;
 // Idle polls back off from one to 32 maximal sleeps (about 3 to 100 us); the
 // limit counts sleeps (about a second in all).
@@ -478,40 +478,49 @@ struct MaxShape {
 
 // STRUCT = false: the launch has no structural work (no heavy prefix and no
 // phase 3), so it needs no LDS and its occupancy is bounded by registers
-// alone.  STRUCT = true: phase 1 over the heavy prefix (possibly empty), and
-// phase 3 when `unified`.
+// alone; one wavefront per workgroup.  STRUCT = true: workgroups of 1, 2 or 4
+// wavefronts share one structural workspace (the LDS and faulty-value slots
+// of one wavefront): wavefront 0 runs phase 1 over the heavy prefix (possibly
+// empty), light faults, then phase 3 when `unified`; the others run light
+// faults only.  Sharing keeps light lanes resident when the structural LDS of
+// a large design would otherwise cap the wavefronts per compute unit.
+constexpr uint32_t kMaxShare = 4;
+
 template <int C, bool BATCH, bool STRUCT>
-__global__ __launch_bounds__(64) void k_twod_a(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
-                                               uint32_t F, const uint32_t* __restrict__ order, TwoDCounters* ctr,
-                                               uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-                                               uint32_t rate_num, int unified,
-                                               uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
+__global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) void k_twod_a(
+    DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
+    const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
+    uint32_t rate_num, int unified, uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
         const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
-        wave_lds_clear(s, mx.N, mx.L, mx.R);
+        const uint32_t wave = threadIdx.x >> 6;
+        if (wave == 0) wave_lds_clear(s, mx.N, mx.L, mx.R);
         __syncthreads();
         Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
         uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
         uint64_t stamp0 = *ws.stamp_dev;
         const uint32_t nh = ctr->n_heavy;
         // Phase 1: heavy faults placed up front.
-        for (;;) {
-            uint32_t idx = 0;
-            if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
-            idx = __shfl(idx, 0, 64);
-            if (idx >= nh) break;
-            heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
-                             events_out);
+        if (wave == 0) {
+            for (;;) {
+                uint32_t idx = 0;
+                if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
+                idx = __shfl(idx, 0, 64);
+                if (idx >= nh) break;
+                heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
+                                 events_out);
+            }
         }
         // Phase 2: light faults, one per lane; each wavefront takes at most
         // its share of lanes so that light faults spread over every wavefront.
         const uint32_t nlight = F - nh;
-        const uint32_t lanes = min(64u, max(1u, (nlight + gridDim.x - 1) / gridDim.x));
+        const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+        const uint32_t lanes = min(64u, max(1u, (nlight + waves - 1) / waves));
         light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
                               events_out, lanes, rate_num);
-        if (unified)
+        if (unified && wave == 0)
             drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
                                   events_out);
     } else {
@@ -660,13 +669,14 @@ static size_t lds_bytes_b(const MaxShape& mx)
 
 // Persistent launches never exceed what can be resident at once: the lane
 // quota assumes every wavefront of the launch runs from the start.
-static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want)
+static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want, uint32_t threads = 64)
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu <= 0 || cus <= 0)
-        return std::min(want, kTicketPad);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)threads, lds) != hipSuccess || per_cu <= 0 ||
+        cus <= 0)
+        return std::max(1u, std::min(want, kTicketPad));
     return std::max(1u, std::min<uint32_t>(std::min(want, kTicketPad), (uint32_t)per_cu * (uint32_t)cus));
 }
 
@@ -682,19 +692,46 @@ static const void* kernel_a_any(int cap, bool batch, bool structural)
     return cap == 4 ? kernel_a<4, false>(structural) : (cap == 16 ? kernel_a<16, false>(structural) : kernel_a<8, false>(structural));
 }
 
-static uint32_t twod_blocks_a(int cap, bool batch, bool structural, const MaxShape& mx, uint32_t want)
+// Launch A's grid for `want` wavefronts: workgroups of 64 * share threads
+// (share 0 with structural work: the smallest of 1, 2, 4 that keeps want
+// wavefronts resident despite the structural LDS, else 4).
+struct GridA {
+    uint32_t blocks = 1, threads = 64;
+};
+
+static GridA twod_grid_a(int cap, bool batch, bool structural, const MaxShape& mx, uint32_t want, int share)
 {
-    const size_t lds = structural ? lds_bytes_a(mx) : 0;
+    GridA g;
     const void* k = kernel_a_any(cap, batch, structural);
-    if (structural && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return std::min(want, kTicketPad);
-    return resident_blocks(k, lds, want);
+    if (!structural) {
+        g.blocks = resident_blocks(k, 0, want);
+        return g;
+    }
+    const size_t lds = lds_bytes_a(mx);
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        g.blocks = std::max(1u, std::min(want, kTicketPad));
+        return g;
+    }
+    uint32_t sh = (uint32_t)share;
+    if (sh == 0) {
+        sh = kMaxShare;
+        for (uint32_t c = 1; c < kMaxShare; c *= 2) {
+            const uint32_t wb = (want + c - 1) / c;
+            if (resident_blocks(k, lds, wb, 64 * c) * c >= want) {
+                sh = c;
+                break;
+            }
+        }
+    }
+    g.threads = 64 * sh;
+    g.blocks = resident_blocks(k, lds, (want + sh - 1) / sh, g.threads);
+    return g;
 }
 
 template <int C, bool BATCH>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
-                                const uint32_t* order, bool heavy, int unified, TwoDCounters* ctr, uint32_t* esc,
-                                int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
+                                const uint32_t* order, bool heavy, int unified, int share, TwoDCounters* ctr,
+                                uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
                                 uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
@@ -702,15 +739,15 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
                                        (int)ldsb);
     if (e != hipSuccess) return e;
     const bool structural = heavy || unified;
-    const uint32_t ba = twod_blocks_a(C, BATCH, structural, mx, blocks);
+    const GridA ga = twod_grid_a(C, BATCH, structural, mx, blocks, share);
     if (unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
-        hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ba), dim3(64), lds, s, src, mx, faults, F, order, ctr,
-                           esc, drop, ws, rate_num, unified, detect, events);
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
+                           order, ctr, esc, drop, ws, rate_num, unified, detect, events);
     } else {
-        hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ba), dim3(64), 0, s, src, mx, faults, F, order, ctr,
-                           esc, drop, ws, rate_num, 0, detect, events);
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
+                           ctr, esc, drop, ws, rate_num, 0, detect, events);
     }
     const uint32_t bb = resident_blocks((const void*)k_twod_b<BATCH>, ldsb, blocks);
     hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(bb), dim3(64), ldsb, s, src, mx, faults, ctr, esc, drop, ws, span,
@@ -722,14 +759,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 
 template <bool BATCH>
 static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
-                                  uint32_t F, const uint32_t* order, bool heavy, int unified, TwoDCounters* ctr,
-                                  uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
-                                  uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
+                                  uint32_t F, const uint32_t* order, bool heavy, int unified, int share,
+                                  TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
+                                  uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
 {
     switch (cap) {
-    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
     }
 }
 
@@ -798,8 +835,8 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const MaxShape mx{d.N, d.L, d.R};
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
-    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, ctr, esc, drop,
-                                          heavy_ws, span, blocks, rate_num, detect, events, s);
+    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share, ctr, esc,
+                                          drop, heavy_ws, span, blocks, rate_num, detect, events, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     return RIROS_OK;
@@ -817,7 +854,9 @@ hipError_t prepare_twod_batch(BatchPlan& b)
     attr((const void*)k_twod_a<16, true, true>, lds_bytes_a(mx));
     attr((const void*)k_twod_b<true>, lds_bytes_b(mx));
     if (e == hipSuccess) {
-        b.blocks_a = twod_blocks_a(b.light_cap, true, b.heavy || b.unified, mx, b.blocks);
+        const GridA ga = twod_grid_a(b.light_cap, true, b.heavy || b.unified, mx, b.blocks, b.share);
+        b.blocks_a = ga.blocks;
+        b.threads_a = ga.threads;
         b.blocks_b = resident_blocks((const void*)k_twod_b<true>, lds_bytes_b(mx), b.blocks);
     }
     return e;
@@ -852,7 +891,8 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
 #define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
-    hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(64), L, s, src, mx, b.faults, b.F, b.order, \
+    hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,     \
+                       b.faults, b.F, b.order,                                                                   \
                        ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events)
     if (b.unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((b.F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, b.F + kTicketPad,

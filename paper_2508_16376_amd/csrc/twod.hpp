@@ -22,6 +22,7 @@ struct TwoDParams {
     float theta = INFINITY;
     int light_cap = 0;
     int unified = 0;            // waves out of light work take handed-over faults during launch A
+    int share = 0;              // launch A wavefronts per structural workspace (0 = as the LDS needs)
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -58,11 +59,13 @@ struct BatchPlan {
     const uint32_t* order = nullptr;
     bool heavy = false;       // a heavy prefix exists (priorities with a finite threshold)
     int unified = 0;          // phase 3 in launch A (see riros_sim_opts.unified)
+    int share = 0;            // launch A wavefronts per structural workspace (see riros_sim_opts.struct_share)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;
     uint32_t blocks = 0;      // launch B (and workspace) grid
     uint32_t blocks_a = 0;    // launch A grid (at most what is resident at once)
+    uint32_t threads_a = 64;  // launch A workgroup size (64 * wavefronts sharing a structural workspace)
     uint32_t blocks_b = 0;    // launch B grid (likewise)
     uint64_t span = 0;        // an upper bound of the stamps one block can use
     PlainWorkspace ws{};

@@ -67,8 +67,9 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 // Simulate fault f from cycle 0 (drop: stop after the detect cycle).  slots
 // is this wave's [N] faulty-value array, regs its [2][R] register next-state
 // ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform) and the
-// event count (wave total).  Must be called by all 64 lanes of a one-wave
-// workgroup (it uses __syncthreads as the wave's LDS fence).
+// event count (wave total).  Must be called by all 64 lanes of one
+// wavefront; other wavefronts of its workgroup may run other work (it orders
+// its LDS accesses with wave_lds_sync, never a workgroup barrier).
 __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gn,
                                       const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                       const riros_fault f, int drop, const WaveLds& s,
@@ -93,7 +94,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     for (uint32_t i = lane; i <= d.L; i += 64) s.lvloff[i] = d.lvl_off[i];
     uint32_t ev = 0;
     uint32_t det = RIROS_UNDETECTED;
-    __syncthreads();
+    wave_lds_sync();
     for (uint32_t t = 0; t < T; ++t) {
         // Cycle start: registers whose D diverged last cycle are scheduled.
         // Lane j owns summary word j, hence register words 32j..32j+31 and
@@ -148,14 +149,14 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         const uint64_t* rst = regs + (size_t)(t & 1) * R;
         uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
         if (lane == 0) s.flags[0] = 0;
-        __syncthreads();
+        wave_lds_sync();
         if (lane == 0) {
             s.sched[site >> 5] |= 1u << (site & 31);
             s.ssum[site >> 10] |= 1u << ((site >> 5) & 31);
             s.lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
             if (anyreg) s.lvlm[0] |= 1u;
         }
-        __syncthreads();
+        wave_lds_sync();
         for (;;) {
             // Lowest level with scheduled nodes (users are always at higher levels).
             int lv = -1;
@@ -171,7 +172,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 }
             }
             if (lv < 0) break;
-            __syncthreads();
+            wave_lds_sync();
             if (lane == 0) s.lvlm[lv >> 5] &= ~(1u << (lv & 31));
             const uint32_t lo = s.lvloff[lv], hi = s.lvloff[lv + 1];
             const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5, s1 = w1 >> 5;
@@ -219,40 +220,41 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     bits &= bits - 1;
                     s.list[off++] = w * 32 + (uint32_t)b;
                 }
-                __syncthreads();
+                wave_lds_sync();
                 for (uint32_t i = lane; i < total; i += 64) {
                     const uint32_t n = s.list[i];
-                    // Record (descriptor + fan-out ranges) in one round trip, then the node's golden
-                    // value, operands and first fan-out entries in a second.  (A per-wave LDS cache
-                    // of records and of the active set's golden and faulty values was measured
-                    // slower: the LDS it takes costs more occupancy than it saves latency.)
+                    // Two dependent round trips per node: the record (descriptor + fan-out ranges,
+                    // with the node's own golden value beside it), then everything the record
+                    // points at, issued together and combined with selects rather than branches,
+                    // so that no load waits for another: operand slots and golden values (an
+                    // operand slot the operator does not read repeats the first operand, or the
+                    // node itself), and the first fan-out entries (the tables end in padding).
+                    // (A per-wave LDS cache of records and of the active set's golden and faulty
+                    // values was measured slower: the LDS it takes costs more occupancy than it
+                    // saves latency.)
                     const NodeRec x = d.rec[n];
                     const uint64_t gv = gold(n);
-                    const uint32_t nf = x.fo1 - x.fo0;
-                    const uint64_t pk0 = nf > 0 ? d.fo_pk[x.fo0] : 0;
-                    const uint64_t pk1 = nf > 1 ? d.fo_pk[x.fo0 + 1] : 0;
-                    bool din = false;
-                    uint64_t v;
-                    if (x.op == RIROS_OP_REG) {
-                        din = (s.rcur[n >> 5] >> (n & 31)) & 1u;
-                        v = din ? rst[n] : gv;
-                    } else if (x.op == RIROS_OP_PI || x.op == RIROS_OP_CONST) {
+                    const bool comb = x.op != RIROS_OP_REG && x.op != RIROS_OP_PI && x.op != RIROS_OP_CONST;
+                    const int ar = comb ? dev_arity(x.op) : 0;
+                    const uint32_t i0 = ar > 0 ? x.a : n;
+                    const uint32_t i1 = ar > 1 ? x.b : i0;
+                    const uint32_t i2 = ar > 2 ? x.c : i0;
+                    const Slot s0 = slots[i0], s1 = slots[i1], s2 = slots[i2];
+                    const uint64_t g0 = gold(i0), g1 = gold(i1), g2 = gold(i2);
+                    const uint64_t pk0 = d.fo_pk[x.fo0], pk1 = d.fo_pk[x.fo0 + 1];
+                    const uint64_t pk2 = d.fo_pk[x.fo0 + 2], pk3 = d.fo_pk[x.fo0 + 3];
+                    const uint32_t rf0 = d.rfo[x.rfo0];
+                    const bool d0 = ar > 0 && s0.stamp == stamp;
+                    const bool d1 = ar > 1 && s1.stamp == stamp;
+                    const bool d2 = ar > 2 && s2.stamp == stamp;
+                    bool din = d0 || d1 || d2;
+                    uint64_t v = apply_opw(x.op, x.width, x.b, x.c, d0 ? s0.v : g0, d1 ? s1.v : g1, d2 ? s2.v : g2);
+                    if (!comb) {
                         v = gv;
-                    } else {
-                        const int ar = dev_arity(x.op);
-                        uint64_t xs[3] = {0, 0, 0};
-                        const uint32_t ins[3] = {x.a, x.b, x.c};
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            if (k < ar) {
-                                const Slot sl = slots[ins[k]];
-                                const uint64_t gx = gold(ins[k]);
-                                const bool dv = sl.stamp == stamp;
-                                xs[k] = dv ? sl.v : gx;
-                                din |= dv;
-                            }
+                        if (x.op == RIROS_OP_REG) {
+                            din = (s.rcur[n >> 5] >> (n & 31)) & 1u;
+                            if (din) v = rst[n];
                         }
-                        v = apply_opw(x.op, x.width, x.b, x.c, xs[0], xs[1], xs[2]);
                     }
                     if (n == site) v = apply_fault(v, fbit, fval, t, ft0);
                     const bool dout = v != gv;
@@ -264,25 +266,26 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         slots[n] = sl;
                         if (x.flags & DF_PO) s.flags[0] = 1;
                         for (uint32_t e = x.fo0; e < x.fo1; ++e) {
-                            const uint64_t pk = e == x.fo0 ? pk0 : (e == x.fo0 + 1 ? pk1 : d.fo_pk[e]);
+                            const uint32_t k = e - x.fo0;
+                            const uint64_t pk = k == 0 ? pk0 : k == 1 ? pk1 : k == 2 ? pk2 : k == 3 ? pk3 : d.fo_pk[e];
                             const uint32_t c = (uint32_t)pk, lc = (uint32_t)(pk >> 32);
                             atomicOr(&s.sched[c >> 5], 1u << (c & 31));
                             atomicOr(&s.ssum[c >> 10], 1u << ((c >> 5) & 31));
                             atomicOr(&s.lvlm[lc >> 5], 1u << (lc & 31));
                         }
                         for (uint32_t e = x.rfo0; e < x.rfo1; ++e) {
-                            const uint32_t r = d.rfo[e];
+                            const uint32_t r = e == x.rfo0 ? rf0 : d.rfo[e];
                             rnx[r] = v;
                             atomicOr(&s.rnext[r >> 5], 1u << (r & 31));
                             atomicOr(&s.rnsum[r >> 10], 1u << ((r >> 5) & 31));
                         }
                     }
                 }
-                __syncthreads();
+                wave_lds_sync();
             }
         }
         if (s.flags[0] && det == RIROS_UNDETECTED) det = t;
-        __syncthreads();
+        wave_lds_sync();
         if (drop && det != RIROS_UNDETECTED) break;
     }
     stamp0 += T;

@@ -50,6 +50,7 @@ class SimOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("drop", ctypes.c_int32), ("io_on_device", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("priority", ctypes.c_void_p), ("theta", ctypes.c_float),
                 ("light_cap", ctypes.c_int32), ("unified", ctypes.c_int32), ("monitor_rate", ctypes.c_float),
+                ("struct_share", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -219,21 +220,22 @@ class Golden:
 
 
 def make_opts(mode=MODE_PLAIN, drop=True, io_on_device=False, waves_per_cu=0, priority=None,
-              theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None) -> SimOpts:
+              theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None, struct_share=0) -> SimOpts:
     return SimOpts(mode, 1 if drop else 0, 1 if io_on_device else 0, waves_per_cu, _ptr(priority),
-                   theta, light_cap, unified, monitor_rate, _stream_ptr(stream))
+                   theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream))
 
 
 def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_PLAIN, drop=True,
               waves_per_cu=0, priority=None, theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0,
-              stream=None, with_events=True):
+              stream=None, with_events=True, struct_share=0):
     """riros_fault_sim on host arrays: returns (detect, events, coverage dict)."""
     fl = np.ascontiguousarray(faults)
     F = fl.size
     detect = np.empty(F, dtype=np.uint32)
     events = np.empty(F, dtype=np.uint64) if with_events else None
     pr = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
-    opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, unified, monitor_rate, stream)
+    opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, unified, monitor_rate, stream,
+                     struct_share)
     cov = Coverage()
     _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(fl), F, ctypes.byref(opts), _ptr(detect),
                                  _ptr(events), ctypes.byref(cov)))
@@ -311,7 +313,7 @@ class Batch:
     """riros_batch_create handle: a campaign of designs run as one graph launch."""
 
     def __init__(self, designs, goldens, fault_lists, priorities=None, *, drop=True, waves_per_cu=0,
-                 theta=math.inf, light_cap=0, monitor_rate=0.0, unified=0):
+                 theta=math.inf, light_cap=0, monitor_rate=0.0, unified=0, struct_share=0):
         n = len(designs)
         fls = [np.ascontiguousarray(f) for f in fault_lists]
         self.F = [int(f.size) for f in fls]
@@ -325,7 +327,8 @@ class Batch:
             prs = [None if p is None else np.ascontiguousarray(p, dtype=np.float32) for p in priorities]
             keep = prs
             pp = (ctypes.c_void_p * n)(*[0 if p is None else p.ctypes.data for p in prs])
-        opts = make_opts(MODE_TWO_D, drop, False, waves_per_cu, None, theta, light_cap, unified, monitor_rate, None)
+        opts = make_opts(MODE_TWO_D, drop, False, waves_per_cu, None, theta, light_cap, unified, monitor_rate, None,
+                         struct_share)
         h = ctypes.c_void_p()
         _check(lib().riros_batch_create(n, dh, gh, fp, _ptr(Fa), pp, ctypes.byref(opts), ctypes.byref(h)))
         del keep

@@ -50,8 +50,9 @@ def test_small_campaign_priorities_and_heavy_split(small_campaign):
     ds, gs = _load(ws)
     prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
     theta = float(np.quantile(np.concatenate(prios), 0.9))
-    for unified in (0, 1):
-        b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=4.0, unified=unified)
+    for unified, share in ((0, 0), (1, 0), (1, 2), (1, 4)):
+        b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=4.0, unified=unified,
+                        struct_share=share)
         for _ in range(2):
             b.launch()
             for i in range(len(ws)):

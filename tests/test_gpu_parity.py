@@ -238,6 +238,20 @@ def test_two_d_unified_with_heavy_prefix_and_small_grid(small):
                theta=0.9, monitor_rate=1.0, unified=1, waves_per_cu=wpc)
 
 
+@pytest.mark.parametrize("share", [1, 2, 4])
+def test_two_d_shared_structural_workspace(small, share):
+    """Launch-A workgroups of 1, 2 or 4 wavefronts share one structural
+    workspace (only the first takes structural work); with a heavy prefix,
+    the unified schedule and the monitor, results are identical."""
+    prio = (W.counter_values(13, 0, small.faults.size) >> np.uint64(40)).astype(np.float32) / np.float32(1 << 24)
+    for unified, theta in ((1, 0.8), (0, 0.5), (1, float("inf"))):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, priority=prio,
+               theta=theta, monitor_rate=1.0, unified=unified, struct_share=share)
+    for wpc in (1, 5):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, False, priority=prio,
+               theta=0.9, monitor_rate=2.0, unified=1, struct_share=share, waves_per_cu=wpc)
+
+
 def test_two_d_unified_medium_full_size():
     w = W.medium()
     _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, monitor_rate=2.0, light_cap=4, unified=1)
@@ -246,7 +260,7 @@ def test_two_d_unified_medium_full_size():
 def test_two_d_rejects_bad_options(tiny):
     d = riros.Design(tiny.design)
     g = riros.Golden(d, tiny.stimulus, tiny.T)
-    for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}):
+    for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}, {"struct_share": 3}, {"struct_share": 8}):
         with pytest.raises(riros.RirosError):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
