@@ -211,18 +211,9 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 }
                 wb += 64;
                 if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
-                const uint32_t cnt = __popc(bits);
-                const uint32_t incl = wave_incl_scan(cnt);
-                const uint32_t total = __shfl(incl, 63, 64);
-                uint32_t off = incl - cnt;
-                while (bits) {
-                    const int b = __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    s.list[off++] = w * 32 + (uint32_t)b;
-                }
-                wave_lds_sync();
-                for (uint32_t i = lane; i < total; i += 64) {
-                    const uint32_t n = s.list[i];
+                // Per node: the faulty value from the operands' faulty or golden
+                // values; a divergent node schedules its users and registers.
+                auto eval_node = [&](const uint32_t n) {
                     // Two dependent round trips per node: the record (descriptor + fan-out ranges,
                     // with the node's own golden value beside it), then everything the record
                     // points at, issued together and combined with selects rather than branches,
@@ -280,6 +271,33 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                             atomicOr(&s.rnsum[r >> 10], 1u << ((r >> 5) & 31));
                         }
                     }
+                };
+                const uint32_t cnt = __popc(bits);
+                if (__ballot(cnt > 2) == 0) {
+                    // Sparse words (at most two scheduled nodes each, the usual
+                    // frontier of a dropped fault): each lane evaluates its own
+                    // word's nodes, in two passes at most, with no compaction.
+                    for (;;) {
+                        const bool act = bits != 0;
+                        if (__ballot(act) == 0) break;
+                        if (act) {
+                            const uint32_t n = w * 32 + (uint32_t)(__ffs(bits) - 1);
+                            bits &= bits - 1;
+                            eval_node(n);
+                        }
+                    }
+                } else {
+                    // Dense words: compact the level's nodes to a list, 64 per pass.
+                    const uint32_t incl = wave_incl_scan(cnt);
+                    const uint32_t total = __shfl(incl, 63, 64);
+                    uint32_t off = incl - cnt;
+                    while (bits) {
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        s.list[off++] = w * 32 + (uint32_t)b;
+                    }
+                    wave_lds_sync();
+                    for (uint32_t i = lane; i < total; i += 64) eval_node(s.list[i]);
                 }
                 wave_lds_sync();
             }
