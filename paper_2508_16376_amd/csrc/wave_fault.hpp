@@ -76,6 +76,20 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                                       Slot* __restrict__ slots, uint64_t* __restrict__ regs,
                                       uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
 {
+    // The LDS arrays as local values rather than fields read through a
+    // reference: code that chooses between two of them then selects
+    // registers, where a choice between two fields' addresses would keep the
+    // structure in scratch memory and reload a pointer on every use.
+    uint32_t* const sched = s.sched;
+    uint32_t* const ssum = s.ssum;
+    uint32_t* const lvlm = s.lvlm;
+    uint32_t* const rcur = s.rcur;
+    uint32_t* const rnext = s.rnext;
+    uint32_t* const rcsum = s.rcsum;
+    uint32_t* const rnsum = s.rnsum;
+    uint32_t* const list = s.list;
+    uint32_t* const flags = s.flags;
+    uint32_t* const lvloff = s.lvloff;
     const uint32_t R = d.R;
     const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32, WRS = (WR + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
@@ -86,12 +100,12 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     // Register state left by the previous fault on this wave: clear the words
     // the summaries point at.
     for (uint32_t j = lane; j < WRS; j += 64) {
-        for (uint32_t m = s.rcsum[j]; m; m &= m - 1) s.rcur[j * 32 + __ffs(m) - 1] = 0;
-        for (uint32_t m = s.rnsum[j]; m; m &= m - 1) s.rnext[j * 32 + __ffs(m) - 1] = 0;
-        s.rcsum[j] = 0;
-        s.rnsum[j] = 0;
+        for (uint32_t m = rcsum[j]; m; m &= m - 1) rcur[j * 32 + __ffs(m) - 1] = 0;
+        for (uint32_t m = rnsum[j]; m; m &= m - 1) rnext[j * 32 + __ffs(m) - 1] = 0;
+        rcsum[j] = 0;
+        rnsum[j] = 0;
     }
-    for (uint32_t i = lane; i <= d.L; i += 64) s.lvloff[i] = d.lvl_off[i];
+    for (uint32_t i = lane; i <= d.L; i += 64) lvloff[i] = d.lvl_off[i];
     uint32_t ev = 0;
     uint32_t det = RIROS_UNDETECTED;
     wave_lds_sync();
@@ -101,19 +115,19 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         // the sched summary word j (registers have the lowest ids).
         uint32_t any = 0;
         for (uint32_t j = lane; j < WRS; j += 64) {
-            for (uint32_t m = s.rcsum[j]; m; m &= m - 1) s.rcur[j * 32 + __ffs(m) - 1] = 0;
-            const uint32_t nm = s.rnsum[j];
+            for (uint32_t m = rcsum[j]; m; m &= m - 1) rcur[j * 32 + __ffs(m) - 1] = 0;
+            const uint32_t nm = rnsum[j];
             for (uint32_t m = nm; m; m &= m - 1) {
                 const uint32_t i = j * 32 + __ffs(m) - 1;
-                const uint32_t v = s.rnext[i];
-                s.rcur[i] = v;
-                s.rnext[i] = 0;
-                s.sched[i] |= v;
+                const uint32_t v = rnext[i];
+                rcur[i] = v;
+                rnext[i] = 0;
+                sched[i] |= v;
                 any |= v;
             }
-            s.rcsum[j] = nm;
-            s.rnsum[j] = 0;
-            s.ssum[j] |= nm;
+            rcsum[j] = nm;
+            rnsum[j] = 0;
+            ssum[j] |= nm;
         }
         const bool anyreg = __ballot(any != 0) != 0;
         if (!anyreg) {
@@ -148,13 +162,13 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         auto gold = [&](uint32_t n) { return Gn[(size_t)n * T + t]; };
         const uint64_t* rst = regs + (size_t)(t & 1) * R;
         uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
-        if (lane == 0) s.flags[0] = 0;
+        if (lane == 0) flags[0] = 0;
         wave_lds_sync();
         if (lane == 0) {
-            s.sched[site >> 5] |= 1u << (site & 31);
-            s.ssum[site >> 10] |= 1u << ((site >> 5) & 31);
-            s.lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
-            if (anyreg) s.lvlm[0] |= 1u;
+            sched[site >> 5] |= 1u << (site & 31);
+            ssum[site >> 10] |= 1u << ((site >> 5) & 31);
+            lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
+            if (anyreg) lvlm[0] |= 1u;
         }
         wave_lds_sync();
         for (;;) {
@@ -162,7 +176,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             int lv = -1;
             for (uint32_t wb = 0; wb < WL; wb += 64) {
                 const uint32_t w = wb + lane;
-                const uint32_t m = w < WL ? s.lvlm[w] : 0u;
+                const uint32_t m = w < WL ? lvlm[w] : 0u;
                 const uint64_t bal = __ballot(m != 0);
                 if (bal) {
                     const int first = __ffsll((unsigned long long)bal) - 1;
@@ -173,8 +187,8 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             }
             if (lv < 0) break;
             wave_lds_sync();
-            if (lane == 0) s.lvlm[lv >> 5] &= ~(1u << (lv & 31));
-            const uint32_t lo = s.lvloff[lv], hi = s.lvloff[lv + 1];
+            if (lane == 0) lvlm[lv >> 5] &= ~(1u << (lv & 31));
+            const uint32_t lo = lvloff[lv], hi = lvloff[lv + 1];
             const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5, s1 = w1 >> 5;
             uint32_t wb = w0;
             for (;;) {
@@ -183,7 +197,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 uint32_t nw = 0xFFFFFFFFu;
                 for (uint32_t sb = wb >> 5; sb <= s1; sb += 64) {
                     const uint32_t sw = sb + lane;
-                    uint32_t sm = sw <= s1 ? s.ssum[sw] : 0u;
+                    uint32_t sm = sw <= s1 ? ssum[sw] : 0u;
                     if (sw == (wb >> 5)) sm &= ~0u << (wb & 31);
                     const uint64_t bal = __ballot(sm != 0);
                     if (bal) {
@@ -202,18 +216,27 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     uint32_t m = ~0u;
                     if (w == w0) m &= ~0u << (lo & 31);
                     if (w == w1 && (hi & 31)) m &= (1u << (hi & 31)) - 1u;
-                    const uint32_t word = s.sched[w];
+                    const uint32_t word = sched[w];
                     bits = word & m;
                     if (bits) {
-                        s.sched[w] = word & ~m;
-                        if ((word & ~m) == 0) atomicAnd(&s.ssum[w >> 5], ~(1u << (w & 31)));
+                        sched[w] = word & ~m;
+                        if ((word & ~m) == 0) atomicAnd(&ssum[w >> 5], ~(1u << (w & 31)));
                     }
                 }
                 wb += 64;
                 if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
-                // Per node: the faulty value from the operands' faulty or golden
-                // values; a divergent node schedules its users and registers.
-                auto eval_node = [&](const uint32_t n) {
+                const uint32_t cnt = __popc(bits);
+                const uint32_t incl = wave_incl_scan(cnt);
+                const uint32_t total = __shfl(incl, 63, 64);
+                uint32_t off = incl - cnt;
+                while (bits) {
+                    const int b = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    list[off++] = w * 32 + (uint32_t)b;
+                }
+                wave_lds_sync();
+                for (uint32_t i = lane; i < total; i += 64) {
+                    const uint32_t n = list[i];
                     // Two dependent round trips per node: the record (descriptor + fan-out ranges,
                     // with the node's own golden value beside it), then everything the record
                     // points at, issued together and combined with selects rather than branches,
@@ -243,7 +266,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     if (!comb) {
                         v = gv;
                         if (x.op == RIROS_OP_REG) {
-                            din = (s.rcur[n >> 5] >> (n & 31)) & 1u;
+                            din = (rcur[n >> 5] >> (n & 31)) & 1u;
                             if (din) v = rst[n];
                         }
                     }
@@ -255,54 +278,27 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         sl.v = v;
                         sl.stamp = stamp;
                         slots[n] = sl;
-                        if (x.flags & DF_PO) s.flags[0] = 1;
+                        if (x.flags & DF_PO) flags[0] = 1;
                         for (uint32_t e = x.fo0; e < x.fo1; ++e) {
                             const uint32_t k = e - x.fo0;
                             const uint64_t pk = k == 0 ? pk0 : k == 1 ? pk1 : k == 2 ? pk2 : k == 3 ? pk3 : d.fo_pk[e];
                             const uint32_t c = (uint32_t)pk, lc = (uint32_t)(pk >> 32);
-                            atomicOr(&s.sched[c >> 5], 1u << (c & 31));
-                            atomicOr(&s.ssum[c >> 10], 1u << ((c >> 5) & 31));
-                            atomicOr(&s.lvlm[lc >> 5], 1u << (lc & 31));
+                            atomicOr(&sched[c >> 5], 1u << (c & 31));
+                            atomicOr(&ssum[c >> 10], 1u << ((c >> 5) & 31));
+                            atomicOr(&lvlm[lc >> 5], 1u << (lc & 31));
                         }
                         for (uint32_t e = x.rfo0; e < x.rfo1; ++e) {
                             const uint32_t r = e == x.rfo0 ? rf0 : d.rfo[e];
                             rnx[r] = v;
-                            atomicOr(&s.rnext[r >> 5], 1u << (r & 31));
-                            atomicOr(&s.rnsum[r >> 10], 1u << ((r >> 5) & 31));
+                            atomicOr(&rnext[r >> 5], 1u << (r & 31));
+                            atomicOr(&rnsum[r >> 10], 1u << ((r >> 5) & 31));
                         }
                     }
-                };
-                const uint32_t cnt = __popc(bits);
-                if (__ballot(cnt > 2) == 0) {
-                    // Sparse words (at most two scheduled nodes each, the usual
-                    // frontier of a dropped fault): each lane evaluates its own
-                    // word's nodes, in two passes at most, with no compaction.
-                    for (;;) {
-                        const bool act = bits != 0;
-                        if (__ballot(act) == 0) break;
-                        if (act) {
-                            const uint32_t n = w * 32 + (uint32_t)(__ffs(bits) - 1);
-                            bits &= bits - 1;
-                            eval_node(n);
-                        }
-                    }
-                } else {
-                    // Dense words: compact the level's nodes to a list, 64 per pass.
-                    const uint32_t incl = wave_incl_scan(cnt);
-                    const uint32_t total = __shfl(incl, 63, 64);
-                    uint32_t off = incl - cnt;
-                    while (bits) {
-                        const int b = __ffs(bits) - 1;
-                        bits &= bits - 1;
-                        s.list[off++] = w * 32 + (uint32_t)b;
-                    }
-                    wave_lds_sync();
-                    for (uint32_t i = lane; i < total; i += 64) eval_node(s.list[i]);
                 }
                 wave_lds_sync();
             }
         }
-        if (s.flags[0] && det == RIROS_UNDETECTED) det = t;
+        if (flags[0] && det == RIROS_UNDETECTED) det = t;
         wave_lds_sync();
         if (drop && det != RIROS_UNDETECTED) break;
     }
