@@ -302,7 +302,7 @@ def main():
         log(f"[bench] predictor: spearman {err['spearman']:.3f}, mean |dlog2| {err['mean_abs_log2']:.3f}")
 
     # Autotuned two-dimensional schedule.
-    tuner = autotune.Autotuner()
+    tuner = autotune.Autotuner(progress=log)
     t = time.perf_counter()
     if args.no_tune:
         params = dict(autotune.DEFAULT)

@@ -64,7 +64,10 @@ def _time_single(d, g, faults, priority, p, reps=2):
 
 
 class Autotuner:
-    def __init__(self, cache_path: str | None = None):
+    def __init__(self, cache_path: str | None = None, progress=None):
+        """progress: optional callable taking one line of text per timed
+        point (a long tuning run then reports as it goes)."""
+        self.progress = progress
         self.cache_path = cache_path
         self.cache: dict[str, dict] = {}
         if cache_path and os.path.exists(cache_path):
@@ -99,6 +102,8 @@ class Autotuner:
                     seen.add(key)
                     t = measure(cand)
                     self.log.append({"params": dict(cand), "ms": t})
+                    if self.progress:
+                        self.progress(f"[autotune] {cand} {t:.3f} ms")
                     if t < best_t:
                         best, best_t = cand, t
             if best == start:
