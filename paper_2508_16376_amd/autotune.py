@@ -25,15 +25,18 @@ import numpy as np
 
 from . import riros
 
+# Descent order: the monitor and capacity first (they decide how much work
+# reaches the structural path), then whether idle wavefronts take it during
+# the light launch, then occupancy and sharing.
 SPACE = {
-    "unified": [1, 0],
     "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
     "light_cap": [4, 8],
+    "unified": [1, 0],
     "waves_per_cu": [8, 12, 16],
     "struct_share": [1, 2, 4],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
-DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 0,
+DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_quantile": None}
 
 

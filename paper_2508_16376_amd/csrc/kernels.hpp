@@ -62,11 +62,11 @@ struct PlainWorkspace {
 hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s);
 
 // Bytes of dynamic LDS the plain kernel needs for a design.
-size_t plain_lds_bytes(const DevDesign& d);
+size_t plain_lds_bytes(const DevDesign& d, uint32_t wpp);
 
 hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
-                              const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
+                              const PlainWorkspace& ws, uint32_t wpp, uint32_t* detect, uint64_t* events,
                               hipStream_t s);
 
 hipError_t launch_validate_faults(const DevDesign& d, const riros_fault* faults, uint32_t F,

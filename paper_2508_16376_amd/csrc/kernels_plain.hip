@@ -103,20 +103,20 @@ hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t
 // Global workspace per block: slots[N] faulty value + validity stamp,
 // regs[2][R] next state of diverged registers (ping-pong by cycle parity).
 // ---------------------------------------------------------------------------
-size_t plain_lds_bytes(const DevDesign& d)
+size_t plain_lds_bytes(const DevDesign& d, uint32_t wpp)
 {
-    return wave_lds_words(d.N, d.L, d.R) * sizeof(uint32_t);
+    return wave_lds_words(d.N, d.L, d.R, wpp) * sizeof(uint32_t);
 }
 
 __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gn,
                                                     const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                                     const riros_fault* __restrict__ faults,
-                                                    uint32_t F, int drop, PlainWorkspace ws,
+                                                    uint32_t F, int drop, PlainWorkspace ws, uint32_t wpp,
                                                     uint32_t* __restrict__ detect_out,
                                                     uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R);
+    const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R, wpp);
     wave_lds_clear(s, d.N, d.L, d.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * d.N;
@@ -146,15 +146,15 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
 
 hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
-                              const PlainWorkspace& ws, uint32_t* detect, uint64_t* events,
+                              const PlainWorkspace& ws, uint32_t wpp, uint32_t* detect, uint64_t* events,
                               hipStream_t s)
 {
-    const size_t lds = plain_lds_bytes(d);
+    const size_t lds = plain_lds_bytes(d, wpp);
     hipError_t e = hipFuncSetAttribute((const void*)k_fault_plain,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, g.Gn, g.Bp, g.T, g.TW, faults, F, drop, ws,
-                       detect, events);
+                       wpp, detect, events);
     return hipGetLastError();
 }
 

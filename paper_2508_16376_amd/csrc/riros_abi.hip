@@ -388,9 +388,13 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     }
 
     if (opts->mode == RIROS_MODE_PLAIN) {
-        const size_t lds = riros::plain_lds_bytes(d->dev);
-        if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the plain kernel's LDS bitmap");
+        if (riros::plain_lds_bytes(d->dev, riros::kWordsNarrow) > 160 * 1024)
+            return set_err(RIROS_EINVAL, "design too large for the plain kernel's LDS bitmap");
         int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 16;
+        // (this kernel's registers allow about twelve wavefronts a compute
+        // unit whatever its LDS, so the wide pass is kept up to that)
+        const uint32_t wpp = riros::words_per_pass(d->img.N, d->img.L, d->img.R, (uint32_t)std::min(wpc, 12));
+        const size_t lds = riros::plain_lds_bytes(d->dev, wpp);
         const int lds_limit = (int)std::max<size_t>(1, (160 * 1024) / lds);
         wpc = std::min(std::min(wpc, lds_limit), 32);
         uint32_t blocks = (uint32_t)std::min<uint64_t>(F, (uint64_t)d->num_cu * wpc);
@@ -399,14 +403,14 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
         riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_dev};
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
-        HIP_TRY(riros::launch_fault_plain(d->dev, g->view(), d_faults, F, opts->drop ? 1 : 0, blocks, ws, d_detect,
-                                          d_events, s),
+        HIP_TRY(riros::launch_fault_plain(d->dev, g->view(), d_faults, F, opts->drop ? 1 : 0, blocks, ws, wpp,
+                                          d_detect, d_events, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
         HIP_TRY(riros::launch_advance_stamp(d->stamp_dev, per_block * T + 1, s), "stamp advance");
     } else {
-        const size_t lds = riros::plain_lds_bytes(d->dev);
-        if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");
+        if (riros::plain_lds_bytes(d->dev, riros::kWordsNarrow) > 160 * 1024)
+            return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");
         // The launches clamp their grids to what is resident at once; the
         // light launch may need no LDS at all, so LDS does not cap this.
         int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 12;
@@ -421,7 +425,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.light_cap = opts->light_cap;
         p.unified = opts->unified;
         p.share = opts->struct_share;
-        p.waves_per_cu = opts->waves_per_cu;
+        p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
         rc = riros::run_twod(d->dev, d->twod, g->view(), d_faults, d_prio, F, opts->drop ? 1 : 0, p, hws,
@@ -653,7 +657,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         Tmax = std::max(Tmax, goldens[i]->T);
     }
     if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
-    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax) * sizeof(uint32_t);
+    const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax, riros::kWordsNarrow) * sizeof(uint32_t);
     if (lds > 160 * 1024) return set_err(RIROS_EINVAL, "largest design too large for the structural path's LDS bitmap");
     DeviceGuard guard(dev);
     riros_batch b = new (std::nothrow) riros_batch_s();
@@ -752,6 +756,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.heavy = d_pr != nullptr && !(opts->theta > 3.0e38f);
     p.unified = opts->unified;
     p.share = opts->struct_share;
+    p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);
     if (e != hipSuccess) return fail(RIROS_EDEVICE, std::string("campaign preparation: ") + hipGetErrorString(e));

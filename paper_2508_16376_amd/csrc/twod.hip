@@ -474,6 +474,7 @@ __device__ void drain_handover(const DesignSrc& src, const riros_fault* __restri
 // Shapes of the largest design of a launch (LDS and workspace are sized by it).
 struct MaxShape {
     uint32_t N, L, R;
+    uint32_t wpp;   // structural schedule words per pass
 };
 
 // STRUCT = false: the launch has no structural work (no heavy prefix and no
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) void k_twod_a(
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
-        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+        const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, mx.wpp);
         const uint32_t wave = threadIdx.x >> 6;
         if (wave == 0) wave_lds_clear(s, mx.N, mx.L, mx.R);
         __syncthreads();
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
                                                uint64_t* __restrict__ events_out)
 {
     extern __shared__ uint32_t lds[];
-    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R);
+    const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, mx.wpp);
     wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
@@ -660,11 +661,11 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
 // LDS of the structural path (launch A with structural work, launch B).
 static size_t lds_bytes_a(const MaxShape& mx)
 {
-    return wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
+    return wave_lds_words(mx.N, mx.L, mx.R, mx.wpp) * sizeof(uint32_t);
 }
 static size_t lds_bytes_b(const MaxShape& mx)
 {
-    return wave_lds_words(mx.N, mx.L, mx.R) * sizeof(uint32_t);
+    return wave_lds_words(mx.N, mx.L, mx.R, mx.wpp) * sizeof(uint32_t);
 }
 
 // Persistent launches never exceed what can be resident at once: the lane
@@ -832,7 +833,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     }
     const uint32_t rate_num = p.monitor_rate > 0.f ? (uint32_t)std::min(4.0e9f, p.monitor_rate * 4.f + 0.5f) : 0u;
     DesignSrc src{d, gw, nullptr, nullptr, nullptr};
-    const MaxShape mx{d.N, d.L, d.R};
+    const MaxShape mx{d.N, d.L, d.R, words_per_pass(d.N, d.L, d.R, (uint32_t)std::max(1, p.waves_per_cu))};
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
     hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share, ctr, esc,
@@ -844,7 +845,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
 
 hipError_t prepare_twod_batch(BatchPlan& b)
 {
-    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
+    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax, b.wpp};
     hipError_t e = hipSuccess;
     auto attr = [&](const void* f, size_t lds) {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -888,7 +889,7 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     uint32_t* esc = (uint32_t*)(base + lay.esc);
     hipLaunchKernelGGL(k_reset_run_counters, dim3(1), dim3(64), 0, s, ctr);
     DesignSrc src{b.td_host0, b.tg_host0, b.td, b.tg, b.did};
-    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax};
+    const MaxShape mx{b.Nmax, b.Lmax, b.Rmax, b.wpp};
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
 #define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,     \

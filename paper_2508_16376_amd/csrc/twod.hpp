@@ -55,6 +55,7 @@ struct BatchPlan {
     const uint16_t* did = nullptr;
     const uint32_t* off = nullptr;
     uint32_t Nmax = 0, Lmax = 0, Rmax = 0;
+    uint32_t wpp = 64;        // structural schedule words per pass
     const riros_fault* faults = nullptr;
     const uint32_t* order = nullptr;
     bool heavy = false;       // a heavy prefix exists (priorities with a finite threshold)

@@ -8,14 +8,22 @@
 
 namespace riros {
 
-constexpr uint32_t kListCap = 2048;
+// Schedule words read per pass (one per lane, 64 or 16) fill a compacted
+// list of up to 32 nodes a word.  The list takes 8 KB of LDS at 64 words and
+// 2 KB at 16; with the bitmaps it decides how many structural wavefronts fit
+// on a compute unit, so the host takes 16 when 64 would cap the wavefronts it
+// wants resident (a dense level then takes more passes of up to 512 nodes).
+constexpr uint32_t kWordsWide = 64, kWordsNarrow = 16;
+// Any other value is taken as the narrow pass (a pass of zero words would
+// never advance).
+__host__ __device__ constexpr uint32_t norm_wpp(uint32_t wpp) { return wpp == kWordsWide ? kWordsWide : kWordsNarrow; }
 
 // LDS of one wave: sched[N/32] nodes to
 // evaluate this cycle, with ssum one bit per non-empty sched word (a sparse
 // frontier in a wide level is found without scanning the level's words);
 // lvlm[L/32] levels holding scheduled nodes; rcur/rnext[R/32] registers whose
 // state diverges in this / the next cycle, with summaries rcsum/rnsum;
-// list[kListCap] compacted node ids; flags; lvloff[L+1] the design's level
+// list[32 * wpp] compacted node ids; flags; lvloff[L+1] the design's level
 // offsets (read once per fault, not per level).
 struct WaveLds {
     uint32_t* sched;
@@ -28,16 +36,26 @@ struct WaveLds {
     uint32_t* list;
     uint32_t* flags;
     uint32_t* lvloff;
+    uint32_t wpp;   // schedule words per pass
 };
 
-__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R)
+__host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R, uint32_t wpp)
 {
     const size_t W = (N + 31) / 32, WR = (R + 31) / 32;
-    return W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + kListCap + 4 +
+    return W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + 32 * (size_t)norm_wpp(wpp) + 4 +
            (L + 1);
 }
 
-__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R)
+// Words per pass for a design: the wide pass unless its LDS would keep fewer
+// than `want` structural wavefronts resident per compute unit.
+inline uint32_t words_per_pass(uint32_t N, uint32_t L, uint32_t R, uint32_t want)
+{
+    constexpr size_t kLdsPerCu = 160 * 1024;
+    const size_t wide = wave_lds_words(N, L, R, kWordsWide) * sizeof(uint32_t);
+    return kLdsPerCu / wide >= want ? kWordsWide : kWordsNarrow;
+}
+
+__device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L, uint32_t R, uint32_t wpp)
 {
     const uint32_t W = (N + 31) / 32, WL = (L + 31) / 32, WR = (R + 31) / 32;
     WaveLds s;
@@ -49,8 +67,9 @@ __device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L,
     s.rcsum = s.rnext + WR;
     s.rnsum = s.rcsum + (WR + 31) / 32;
     s.list = s.rnsum + (WR + 31) / 32;
-    s.flags = s.list + kListCap;
+    s.flags = s.list + 32 * norm_wpp(wpp);
     s.lvloff = s.flags + 4;
+    s.wpp = norm_wpp(wpp);
     return s;
 }
 
@@ -90,6 +109,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     uint32_t* const list = s.list;
     uint32_t* const flags = s.flags;
     uint32_t* const lvloff = s.lvloff;
+    const uint32_t wpp = s.wpp;
     const uint32_t R = d.R;
     const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32, WRS = (WR + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
@@ -209,10 +229,10 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 }
                 if (nw > w1) break;
                 wb = nw;
-                // Words wb..wb+63 of this level: one per lane.
+                // Words wb..wb+wpp-1 of this level: one per lane.
                 const uint32_t w = wb + lane;
                 uint32_t bits = 0;
-                if (w <= w1) {
+                if (lane < wpp && w <= w1) {
                     uint32_t m = ~0u;
                     if (w == w0) m &= ~0u << (lo & 31);
                     if (w == w1 && (hi & 31)) m &= (1u << (hi & 31)) - 1u;
@@ -223,7 +243,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         if ((word & ~m) == 0) atomicAnd(&ssum[w >> 5], ~(1u << (w & 31)));
                     }
                 }
-                wb += 64;
+                wb += wpp;
                 if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
                 const uint32_t cnt = __popc(bits);
                 const uint32_t incl = wave_incl_scan(cnt);

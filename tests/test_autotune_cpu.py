@@ -14,7 +14,7 @@ def test_descent_finds_the_coordinatewise_minimum():
 
     t = autotune.Autotuner()
     best, bt = t._descend(cost, with_priority=True)
-    assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 0,
+    assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 1,
                     "heavy_quantile": 0.99}
     assert bt == 0
     # every candidate is a point of the space, and no point is timed twice

@@ -265,6 +265,16 @@ def test_two_d_rejects_bad_options(tiny):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_narrow_schedule_passes(small, mode):
+    """32 wavefronts per compute unit make the structural LDS take the narrow
+    pass (16 schedule words, a 2 KB list); dense levels (no dropping) then
+    take several passes.  Results are identical."""
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults[:1500], mode, drop, waves_per_cu=32,
+               **({} if mode == riros.MODE_PLAIN else {"unified": 1, "monitor_rate": 1.0, "light_cap": 4}))
+
+
 def test_two_d_waves_per_cu(small):
     for wpc in (1, 3):
         _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, waves_per_cu=wpc)
