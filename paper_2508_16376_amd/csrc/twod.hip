@@ -168,6 +168,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     LaneDesign d = lane_design(src.d, src.g);
 
     uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, ft0 = 0, t = 0, det = RIROS_UNDETECTED;
+    uint32_t rk = 0;   // next entry of rcur to evaluate in this cycle
     uint64_t ev = 0;
     bool in_cycle = false;
     uint64_t exw = 0;
@@ -232,6 +233,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     det = RIROS_UNDETECTED;
                     ev = 0;
                     pend.n = div.n = rcur.n = rnxt.n = 0;
+                    rk = 0;
                     in_cycle = false;
                     ewb = kNone;
                 }
@@ -296,10 +298,14 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 on_divergent(site, 1ull << fbit, srec, sf0, sf1, sf2, sf3);
                 evaluated = true;
             } else {
-#pragma unroll
-                for (int k = 0; k < CR; ++k)
-                    if ((uint32_t)k < rcur.n) (void)pend.insert(rcur.id[k]);
-                if (!pend.insert(site)) esc_now = true;
+                // Divergent registers are evaluated first, straight from
+                // rcur (registers have the lowest ids, and their order among
+                // themselves does not matter); the site joins the pending
+                // set unless it is one of them.
+                rk = 0;
+                bool site_reg = false;
+                (void)rcur.find(site, site_reg);
+                if (!site_reg && !pend.insert(site)) esc_now = true;
             }
             in_cycle = true;
         }
@@ -310,7 +316,15 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             // operator does not read repeats the first operand, or the node
             // itself; the fan-out table ends in padding), so no load waits
             // for another.
-            const uint32_t n = pend.pop_min();
+            uint32_t n = 0;
+            if (rk < rcur.n) {
+#pragma unroll
+                for (int k = 0; k < CR; ++k)
+                    if ((uint32_t)k == rk) n = rcur.id[k];
+                rk++;
+            } else {
+                n = pend.pop_min();
+            }
             const NodeRec r = d.rec[n];
             const uint32_t T = d.T;
             const uint64_t gv = d.Gn[(size_t)n * T + t];
@@ -351,7 +365,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             finished = true;
             continue;
         }
-        if (in_cycle && pend.n == 0) {
+        if (in_cycle && pend.n == 0 && rk >= rcur.n) {
             // End of cycle t.
             bool done = drop && det != RIROS_UNDETECTED;
             if (!done) {
@@ -487,8 +501,11 @@ struct MaxShape {
 // a large design would otherwise cap the wavefronts per compute unit.
 constexpr uint32_t kMaxShare = 4;
 
+// Capacities up to 8 are held to three wavefronts per SIMD (at most 168
+// registers per lane; checked free of spills).
 template <int C, bool BATCH, bool STRUCT>
-__global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) void k_twod_a(
+__global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu_waves_per_eu(C <= 8 ? 3 : 1)))
+void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
     const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
     uint32_t rate_num, int unified, uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
