@@ -108,7 +108,8 @@ size_t plain_lds_bytes(const DevDesign& d, uint32_t wpp)
     return wave_lds_words(d.N, d.L, d.R, wpp) * sizeof(uint32_t);
 }
 
-__global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gn,
+__global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t* __restrict__ Gr,
+                                                    const uint64_t* __restrict__ Gn,
                                                     const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                                     const riros_fault* __restrict__ faults,
                                                     uint32_t F, int drop, PlainWorkspace ws, uint32_t wpp,
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
     for (uint32_t fi = blockIdx.x; fi < F; fi += gridDim.x) {
         uint32_t det;
         uint64_t ev;
-        wave_sim_fault(d, Gn, Bp, T, TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(d, Gr, Gn, Bp, T, TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
         if (threadIdx.x == 0) {
             detect_out[fi] = det;
             if (events_out) events_out[fi] = ev;
@@ -153,7 +154,7 @@ hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
     hipError_t e = hipFuncSetAttribute((const void*)k_fault_plain,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, g.Gn, g.Bp, g.T, g.TW, faults, F, drop, ws,
+    hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, g.G, g.Gn, g.Bp, g.T, g.TW, faults, F, drop, ws,
                        wpp, detect, events);
     return hipGetLastError();
 }

@@ -399,9 +399,9 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
         const uint32_t k = src.did[fi];
         const DevDesign dd = src.td[k];
         const GoldenView gg = src.tg[k];
-        wave_sim_fault(dd, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(dd, gg.G, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     } else {
-        wave_sim_fault(src.d, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(src.d, src.g.G, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
     }
     if (threadIdx.x == 0) {
         detect_out[fi] = det;

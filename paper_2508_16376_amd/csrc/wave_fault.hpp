@@ -89,7 +89,8 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 // event count (wave total).  Must be called by all 64 lanes of one
 // wavefront; other wavefronts of its workgroup may run other work (it orders
 // its LDS accesses with wave_lds_sync, never a workgroup barrier).
-__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gn,
+__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gr,
+                                      const uint64_t* __restrict__ Gn,
                                       const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                       const riros_fault f, int drop, const WaveLds& s,
                                       Slot* __restrict__ slots, uint64_t* __restrict__ regs,
@@ -177,9 +178,6 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
             if (!found) break;
         }
         const uint64_t stamp = stamp0 + t + 1;
-        // Node-major golden values: a node evaluated in consecutive cycles
-        // reads one cache line per eight cycles.
-        auto gold = [&](uint32_t n) { return Gn[(size_t)n * T + t]; };
         const uint64_t* rst = regs + (size_t)(t & 1) * R;
         uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
         if (lane == 0) flags[0] = 0;
@@ -255,6 +253,13 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     list[off++] = w * 32 + (uint32_t)b;
                 }
                 wave_lds_sync();
+                // A dense pass (more nodes than lanes) reads golden values from
+                // the cycle-major trace, where a level's nodes are neighbours
+                // and the cycle's row is shared by every fault near that
+                // cycle; a sparse one from the node-major trace, where a node
+                // keeps its line for sixteen cycles.
+                const bool dense = total > 64;
+                auto goldp = [&](uint32_t n) { return dense ? Gr[(size_t)t * d.N + n] : Gn[(size_t)n * T + t]; };
                 for (uint32_t i = lane; i < total; i += 64) {
                     const uint32_t n = list[i];
                     // Two dependent round trips per node: the record (descriptor + fan-out ranges,
@@ -267,14 +272,14 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     // values was measured slower: the LDS it takes costs more occupancy than it
                     // saves latency.)
                     const NodeRec x = d.rec[n];
-                    const uint64_t gv = gold(n);
+                    const uint64_t gv = goldp(n);
                     const bool comb = x.op != RIROS_OP_REG && x.op != RIROS_OP_PI && x.op != RIROS_OP_CONST;
                     const int ar = comb ? dev_arity(x.op) : 0;
                     const uint32_t i0 = ar > 0 ? x.a : n;
                     const uint32_t i1 = ar > 1 ? x.b : i0;
                     const uint32_t i2 = ar > 2 ? x.c : i0;
                     const Slot s0 = slots[i0], s1 = slots[i1], s2 = slots[i2];
-                    const uint64_t g0 = gold(i0), g1 = gold(i1), g2 = gold(i2);
+                    const uint64_t g0 = goldp(i0), g1 = goldp(i1), g2 = goldp(i2);
                     const uint64_t pk0 = d.fo_pk[x.fo0], pk1 = d.fo_pk[x.fo0 + 1];
                     const uint64_t pk2 = d.fo_pk[x.fo0 + 2], pk3 = d.fo_pk[x.fo0 + 3];
                     const uint32_t rf0 = d.rfo[x.rfo0];
