@@ -28,10 +28,11 @@ struct DevDesign {
 };
 
 // Golden trace in three layouts: row-major G[t][n] (what the golden kernel
-// writes and riros_golden_read returns), node-major Gn[n][t] (read by every
-// fault kernel: a node evaluated in consecutive cycles stays in one cache
-// line for eight cycles), and bit-planes
-// Bp[row][w] with row = bp_off[n] + bit, word w holding cycles 64w..64w+63.
+// writes and riros_golden_read returns; the structural path reads it in
+// dense passes, where a level's nodes are neighbours), node-major Gn[n][t]
+// (read by every sparse evaluation: a node evaluated in consecutive cycles
+// stays in one cache line for sixteen cycles), and bit-planes Bp[row][w]
+// with row = bp_off[n] + bit, word w holding cycles 64w..64w+63.
 struct GoldenView {
     const uint64_t* G;
     const uint64_t* Gn;
