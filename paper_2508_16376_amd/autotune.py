@@ -83,10 +83,11 @@ class Autotuner:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1, sort_keys=True)
 
-    def _descend(self, measure, with_priority: bool):
+    def _descend(self, measure, with_priority: bool, confirm: int = 3):
         best = dict(DEFAULT)
         best_t = measure(best)
         self.log.append({"params": dict(best), "ms": best_t})
+        timed = [(best_t, dict(best))]
         seen = {tuple(sorted(best.items(), key=lambda kv: kv[0]))}
         # Two passes at most: a parameter chosen early (say the monitor rate)
         # may lose its worth once a later one moves (most faults starting on
@@ -105,12 +106,24 @@ class Autotuner:
                     seen.add(key)
                     t = measure(cand)
                     self.log.append({"params": dict(cand), "ms": t})
+                    timed.append((t, dict(cand)))
                     if self.progress:
                         self.progress(f"[autotune] {cand} {t:.3f} ms")
                     if t < best_t:
                         best, best_t = cand, t
             if best == start:
                 break
+        # The fastest few points are timed twice more and ranked by their
+        # mean: a single lucky timing should not pick the schedule.
+        if confirm > 1:
+            top = sorted(timed, key=lambda x: x[0])[:confirm]
+            scored = []
+            for t0, p in top:
+                ts = [t0] + [measure(p) for _ in range(2)]
+                scored.append((sum(ts) / len(ts), min(ts), p))
+                if self.progress:
+                    self.progress(f"[autotune] confirm {p} mean {scored[-1][0]:.3f} ms")
+            _, best_t, best = min(scored, key=lambda x: x[0])
         return best, best_t
 
     def tune_single(self, design_np, d, g, faults, priority=None, T=None):

@@ -17,9 +17,12 @@ def test_descent_finds_the_coordinatewise_minimum():
     assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 1,
                     "heavy_quantile": 0.99}
     assert bt == 0
-    # every candidate is a point of the space, and no point is timed twice
+    # every candidate is a point of the space; the descent times no point
+    # twice, and then the three fastest points are timed twice more each
     keys = [tuple(sorted(c.items(), key=lambda kv: kv[0])) for c in calls]
-    assert len(keys) == len(set(keys))
+    distinct = len(set(keys))
+    assert len(keys) == distinct + 2 * min(3, distinct)
+    assert keys[:distinct] == list(dict.fromkeys(keys))
     for c in calls:
         for k, v in c.items():
             assert v in autotune.SPACE[k] or v == autotune.DEFAULT[k]
@@ -39,3 +42,23 @@ def test_cache_round_trip(tmp_path):
     t.cache["k"] = {"params": dict(autotune.DEFAULT)}
     t._save()
     assert autotune.Autotuner(path).cache["k"]["params"] == autotune.DEFAULT
+
+
+def test_confirmation_ranks_by_mean_not_by_a_lucky_timing():
+    """A point that timed fast once but is slow on average loses to a point
+    that is steadily fast."""
+    lucky = {"monitor_rate": 1.0}
+    seen = {}
+
+    def cost(p):
+        k = tuple(sorted(p.items(), key=lambda kv: kv[0]))
+        seen[k] = seen.get(k, 0) + 1
+        if dict(p, monitor_rate=2.0) == autotune.DEFAULT and p["monitor_rate"] == 1.0:
+            return 1.0 if seen[k] == 1 else 10.0     # one point, fast only the first time
+        return 3.0 if p["monitor_rate"] == 4.0 else 5.0
+
+    t = autotune.Autotuner()
+    best, bt = t._descend(cost, with_priority=False)
+    assert best["monitor_rate"] == 4.0
+    assert bt == 3.0
+    assert lucky["monitor_rate"] != best["monitor_rate"]
