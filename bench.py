@@ -250,9 +250,8 @@ def main():
                     help="only run one copy of known size (for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the fault list would be "
-              "sharded by fault across GPUs with one final gather, which this build does not include.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the fault list across "
+              "GPUs (by fault, with one final gather) is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
