@@ -126,6 +126,17 @@ int riros_golden_read(riros_golden g, uint32_t t0, uint32_t nt, uint64_t* out);
 #define RIROS_MODE_PLAIN 0     /* one fault per wavefront, static fault order */
 #define RIROS_MODE_TWO_D 1     /* light faults one per lane, heavy faults split
                                   structurally; persistent work queue */
+#define RIROS_MODE_CONCURRENT 2 /* node-major concurrent simulation (good gate and
+                                  bad gates of a node together, Sec. II-B and
+                                  Sec. IV-B): faults ordered by site, 64 to a
+                                  wavefront, one per lane, walking the union of
+                                  their divergent frontiers; each frontier node is
+                                  fetched once for all 64.  Takes up to 48 GiB of
+                                  device memory for faulty state (about
+                                  528 * (num_nodes + 2 * registers) bytes per
+                                  resident wavefront); waves_per_cu bounds the
+                                  wavefronts; priority and the TWO_D fields are
+                                  ignored */
 
 typedef struct {
     int32_t mode;          /* RIROS_MODE_* */
@@ -176,8 +187,11 @@ typedef struct {
  * simulation); with drop = 1 the count stops after the detect cycle.
  * cov (may be NULL) receives totals.  Results do not depend on mode, priority,
  * theta, light_cap, unified, monitor_rate or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
- * bit >= width, stuck > 2, unknown mode, design/golden mismatch), RIROS_ENOMEM,
- * RIROS_EDEVICE. */
+ * bit >= width, stuck > 2, unknown mode, design/golden mismatch, a design
+ * whose frontier bitmaps exceed a compute unit's 160 KB of LDS), RIROS_ENOMEM
+ * (also: CONCURRENT when one wavefront's faulty state exceeds its 48 GiB),
+ * RIROS_EDEVICE.  Calls on one design share its workspace: issue them on one
+ * stream, or wait for one before the next. */
 int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
                     const riros_sim_opts* opts, uint32_t* detect, uint64_t* events,
                     riros_coverage* cov);

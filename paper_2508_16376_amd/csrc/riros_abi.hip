@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "concurrent.hpp"
 #include "design.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
@@ -98,6 +99,8 @@ struct riros_design_s {
     uint64_t* stamp_dev = nullptr;   // slot stamps above this are unused (advanced on the device by every run)
     // two-dimensional kernel workspace
     riros::TwoDWorkspace twod{};
+    // concurrent (node-major) mode workspace
+    riros::ConcWorkspace conc{};
     // staging for host-side inputs and outputs
     void* stage = nullptr;
     size_t stage_cap = 0;
@@ -135,6 +138,7 @@ static void free_design_mem(riros_design d)
     if (d->d_bad) (void)hipFree(d->d_bad);
     if (d->d_nodefeat) (void)hipFree(d->d_nodefeat);
     riros::twod_free(d->twod);
+    riros::conc_free(d->conc);
 }
 
 extern "C" {
@@ -323,7 +327,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (!d || !g || !opts) return set_err(RIROS_EINVAL, "NULL argument");
     if (g->d != d) return set_err(RIROS_EINVAL, "golden trace belongs to another design");
     if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
-    if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D)
+    if (opts->mode != RIROS_MODE_PLAIN && opts->mode != RIROS_MODE_TWO_D && opts->mode != RIROS_MODE_CONCURRENT)
         return set_err(RIROS_EINVAL, "unknown mode");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
@@ -408,6 +412,11 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
         HIP_TRY(riros::launch_advance_stamp(d->stamp_dev, per_block * T + 1, s), "stamp advance");
+    } else if (opts->mode == RIROS_MODE_CONCURRENT) {
+        std::string err;
+        const int rc = riros::run_concurrent(d->dev, d->conc, g->view(), d_faults, F, opts->drop ? 1 : 0,
+                                             opts->waves_per_cu, d->num_cu, d_detect, d_events, g_ev0, g_ev1, s, err);
+        if (rc) return set_err(rc, err);
     } else {
         if (riros::plain_lds_bytes(d->dev, riros::kWordsNarrow) > 160 * 1024)
             return set_err(RIROS_EINVAL, "design too large for the heavy kernel's LDS bitmap");

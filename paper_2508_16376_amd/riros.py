@@ -25,6 +25,7 @@ RIROS_EDEVICE = -4
 UNDETECTED = 0xFFFFFFFF
 MODE_PLAIN = 0
 MODE_TWO_D = 1
+MODE_CONCURRENT = 2
 
 EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros_free_golden",
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",

@@ -80,3 +80,9 @@ def test_malformed_design_rejected(case):
     rc, msg = _load(d)
     assert rc == riros.RIROS_EINVAL, (case, rc, msg)
     assert msg
+
+
+def test_mode_constants_match_the_header():
+    text = open(os.path.join(ROOT, "include", "riros.h")).read()
+    modes = {m: int(v) for m, v in re.findall(r"#define RIROS_MODE_(\w+) (\d+)", text)}
+    assert modes == {"PLAIN": riros.MODE_PLAIN, "TWO_D": riros.MODE_TWO_D, "CONCURRENT": riros.MODE_CONCURRENT}

@@ -13,7 +13,8 @@ from paper_2508_16376_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 UND = riros.UNDETECTED
-MODES = [riros.MODE_PLAIN, riros.MODE_TWO_D]
+MODES = [pytest.param(riros.MODE_PLAIN, id="plain"), pytest.param(riros.MODE_TWO_D, id="two_d"),
+         pytest.param(riros.MODE_CONCURRENT, id="concurrent")]
 
 
 def _run(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, **kw):
@@ -321,7 +322,9 @@ def test_flips_tiny_every_site_bit_and_cycle_window(tiny, mode, drop):
 
 @pytest.mark.parametrize("kw", [{"mode": riros.MODE_PLAIN}, {"mode": riros.MODE_TWO_D},
                                 {"mode": riros.MODE_TWO_D, "monitor_rate": 1.0, "unified": 1},
-                                {"mode": riros.MODE_TWO_D, "light_cap": 4, "monitor_rate": 0.5}])
+                                {"mode": riros.MODE_TWO_D, "light_cap": 4, "monitor_rate": 0.5},
+                                {"mode": riros.MODE_CONCURRENT}],
+                         ids=["plain", "two_d", "two_d_unified", "two_d_cap4", "concurrent"])
 def test_flips_and_stuck_mixed_small(small, kw):
     w = small
     fl = np.concatenate([w.faults[:2000], W.gen_flip_faults(17, w.design, 3000, w.T + 30)])
