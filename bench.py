@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-drop-leg", choices=["on", "off"], default="on",
                     help="extra run without fault dropping (the paper's convention) on a sample of the faults")
+    ap.add_argument("--concurrent-leg", choices=["on", "off"], default="on",
+                    help="extra timing of the concurrent (node-major) mode on the same workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one copy of known size (for scaling the HBM byte counters)")
     args = ap.parse_args()
@@ -351,6 +353,19 @@ def main():
                   "detect_identical": bool(np.array_equal(ndet, best["detect"][0][idx]))}
         log(f"[bench] no-drop sample of {n}: kernel {nd_ms:.3f} ms, {nodrop['nominal_fault_cycles_per_s']:.4g} F*T/s")
 
+    # The node-major alternative (faults grouped by site, 64 to a wavefront,
+    # over the union of their frontiers) on the same inputs: at most two timed
+    # steps, since it can be several times slower.
+    conc = None
+    if args.concurrent_leg != "off" and not multi:
+        csteps = min(args.steps, 2)
+        cr = job.run(riros.MODE_CONCURRENT, csteps, 1, {})
+        conc = {"fault_cycles_per_s": rate(cr, csteps), "kernel_ms": cr["kernel_ms"], "steps": csteps,
+                "identical_to_two_d": bool(np.array_equal(cr["detect"][0], best["detect"][0]) and
+                                           np.array_equal(cr["events_arr"][0], best["events_arr"][0]))}
+        same = same and conc["identical_to_two_d"]
+        log(f"[bench] concurrent: kernel {cr['kernel_ms']:.3f} ms, rate {conc['fault_cycles_per_s']:.4g} FC/s")
+
     FC, E = best["fault_cycles"], best["events"]
     value = rate(best, args.steps)
     alg_bytes = BYTES_PER_FC * FC + BYTES_PER_EVENT * E
@@ -374,6 +389,7 @@ def main():
         "autotuned": {"params": params, "tune_s": tune_s},
         "predictor": pred_info,
         "no_drop": nodrop,
+        "concurrent": conc,
         "results_identical_across_modes": bool(same),
         "golden_s": job.golden_s, "fault_cycles": FC, "events": E, "detected": best["detected"],
     }
