@@ -33,6 +33,13 @@ HBM_PEAK_GBS = 8000.0
 # words, one faulty-value write).
 BYTES_PER_FC = 8
 BYTES_PER_EVENT = 32
+# Algorithmic integer operations: about 10 per event (input selects, the
+# operator, the compare with the golden value, scheduling the users) and 3
+# per fault-cycle (the excitation check), against the vector ALUs' int32
+# rate: 256 compute units x 64 lanes a clock x 2.4 GHz.
+OPS_PER_EVENT = 10
+OPS_PER_FC = 3
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
 NO_DROP_SAMPLE = 2000
 
 WORKLOADS = {
@@ -83,6 +90,23 @@ def measured_traffic(workload):
 
 
 COPY_BYTES = 1 << 30
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def copy_calibration():
@@ -378,6 +402,11 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "designs": len(ws), "faults": int(total_faults),
                    "mode": "two-dimensional, predictor-ordered, autotuned" + (", one graph launch" if multi else "")},
+        "valu": {"ops_alg": OPS_PER_EVENT * E + OPS_PER_FC * FC,
+                 "achieved": (OPS_PER_EVENT * E + OPS_PER_FC * FC) / (best["kernel_ms"] * 1e-3),
+                 "peak": VALU_PEAK_OPS, "unit": "int32 op/s",
+                 "frac": (OPS_PER_EVENT * E + OPS_PER_FC * FC) / (best["kernel_ms"] * 1e-3) / VALU_PEAK_OPS},
+        "host": host_info(),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_twod_a+k_twod_b", "kernel_ms": best["kernel_ms"],
@@ -427,6 +456,24 @@ def main():
         out["cpu_baseline"] = {"value": cpu_fc / cpu_s, "unit": "fault-cycles/s", "cores": nt, "kind": "oracle",
                                "sample": f"{nsample} of {total_faults} faults of the same workload (seeded uniform "
                                          f"draw), oracle O1 (divergent nodes only), {cpu_s:.2f}s wall on {nt} threads"}
+        # One host thread on the first faults of the same seeded draw of the
+        # first design (the paper compares 1 and 16 cores), about 3 s.
+        w = ws[0]
+        G = oracle.golden(w.design, w.stimulus, w.T)
+        perm = np.argsort(W.counter_values(0xBA5E, 0, w.faults.size))
+        fc1, s1, n1, n = 0, 0.0, 0, min(w.faults.size, 100)
+        while n1 < w.faults.size and s1 < 3.0:
+            idx = np.sort(perm[n1:n1 + n])
+            t = time.perf_counter()
+            odet, _ = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults[idx], G=G, variant=1, nthreads=1)
+            s1 += time.perf_counter() - t
+            fc1 += oracle.fault_cycles(odet, w.T)
+            n1 += idx.size
+            exact &= bool(np.array_equal(odet, best["detect"][0][idx]))
+            n = min(w.faults.size - n1, 2 * n)
+        del G
+        out["cpu_1thread"] = {"value": fc1 / s1, "unit": "fault-cycles/s", "cores": 1, "kind": "oracle",
+                              "sample": f"{n1} faults of the same seeded draw, {s1:.2f}s on one thread"}
         out["parity"] = "bit-exact" if exact else "MISMATCH"
         if not exact:
             log("[bench] detect/events differ from the oracle")
