@@ -1,8 +1,8 @@
 """GPU parity of the concurrent (node-major) mode beyond the shared matrix of
 tests/test_gpu_parity.py: wavefronts that take several groups in turn (their
 stamps carry over), a workspace that grows and is reused, device-resident
-inputs and outputs, and the heavy-tailed list at full size against the
-oracle's stored sample."""
+inputs and outputs, and the heavy-tailed and large lists at full size
+against the oracle's stored samples."""
 import numpy as np
 import pytest
 import torch
@@ -102,8 +102,8 @@ def test_one_site_many_faults():
         np.testing.assert_array_equal(ev, oev)
 
 
-def test_heavy_tailed_full_size_against_stored_oracle_sample():
-    name = "heavy_tailed"
+@pytest.mark.parametrize("name", ["heavy_tailed", "large"])
+def test_full_size_against_stored_oracle_sample(name):
     digest, idx, odet, oev = make_expected.read(name)
     w = make_expected.MAKERS[name][0]()
     assert make_expected.workload_digest(w) == digest, \
