@@ -131,12 +131,12 @@ int riros_golden_read(riros_golden g, uint32_t t0, uint32_t nt, uint64_t* out);
                                   Sec. IV-B): faults ordered by site, 64 to a
                                   wavefront, one per lane, walking the union of
                                   their divergent frontiers; each frontier node is
-                                  fetched once for all 64.  Takes up to 48 GiB of
-                                  device memory for faulty state (about
-                                  528 * (num_nodes + 2 * registers) bytes per
-                                  resident wavefront); waves_per_cu bounds the
-                                  wavefronts; priority and the TWO_D fields are
-                                  ignored */
+                                  fetched once for all 64.  Takes up to 128 GiB,
+                                  and at most 60% of the free device memory, for
+                                  faulty state (about 528 * (num_nodes + 2 *
+                                  registers) bytes per resident wavefront);
+                                  waves_per_cu bounds the wavefronts; priority
+                                  and the TWO_D fields are ignored */
 
 typedef struct {
     int32_t mode;          /* RIROS_MODE_* */
@@ -189,7 +189,7 @@ typedef struct {
  * theta, light_cap, unified, monitor_rate or waves_per_cu.  Errors: RIROS_EINVAL (site >= num_nodes,
  * bit >= width, stuck > 2, unknown mode, design/golden mismatch, a design
  * whose frontier bitmaps exceed a compute unit's 160 KB of LDS), RIROS_ENOMEM
- * (also: CONCURRENT when one wavefront's faulty state exceeds its 48 GiB),
+ * (also: CONCURRENT when one wavefront's faulty state exceeds its budget),
  * RIROS_EDEVICE.  Calls on one design share its workspace: issue them on one
  * stream, or wait for one before the next. */
 int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,

@@ -358,7 +358,14 @@ int run_concurrent(const DevDesign& d, ConcWorkspace& ws, const GoldenView& gv, 
     }
     const int wpc = waves_per_cu > 0 ? std::min(waves_per_cu, occ) : occ;
     const uint64_t groups = ((uint64_t)F + 63) / 64;
-    const uint64_t by_mem = kConcMaxSimBytes / conc_slot_bytes(d.N, d.R);
+    // Dense faulty state decides how many groups are resident, and
+    // residency hides a node's latency: the budget is large, but never more
+    // than 60% of the free memory (with the current state counted as free).
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { err = "device memory query"; return RIROS_EDEVICE; }
+    const size_t held = (ws.sim && ws.N == d.N && ws.R == d.R) ? ws.sim_bytes : 0;
+    const size_t budget = std::min(kConcMaxSimBytes, (free_b + held) / 10 * 6);
+    const uint64_t by_mem = budget / conc_slot_bytes(d.N, d.R);
     const uint32_t slots = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(groups, (uint64_t)num_cu * wpc), by_mem);
     if (slots == 0) { err = "design too large for the concurrent mode's faulty state"; return RIROS_ENOMEM; }
 

@@ -32,12 +32,13 @@ size_t conc_lds_bytes(uint32_t N, uint32_t R);
 // Device bytes of one slot's faulty state.
 size_t conc_slot_bytes(uint32_t N, uint32_t R);
 
-// Largest device memory the concurrent mode takes for faulty state.
-constexpr size_t kConcMaxSimBytes = 48ull << 30;
+// Largest device memory the concurrent mode takes for faulty state: this,
+// and at most 60% of what the device has free when the state is laid out.
+constexpr size_t kConcMaxSimBytes = 128ull << 30;
 
 // Order the faults by site and simulate them in groups of 64.  waves_per_cu
 // bounds the resident wavefronts per compute unit (0 = as many as LDS and
-// kConcMaxSimBytes allow).  ev0/ev1 bracket the sort and the kernel.
+// the faulty-state budget allow).  ev0/ev1 bracket the sort and the kernel.
 int run_concurrent(const DevDesign& d, ConcWorkspace& ws, const GoldenView& gv, const riros_fault* faults,
                    uint32_t F, int drop, int waves_per_cu, int num_cu, uint32_t* detect, uint64_t* events,
                    hipEvent_t ev0, hipEvent_t ev1, hipStream_t s, std::string& err);
