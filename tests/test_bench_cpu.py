@@ -1,0 +1,40 @@
+"""Host-side parts of the benchmark: the committed traffic counters are used
+only for the kernel sources they were taken on, and more than one GPU is
+refused with a message."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_traffic_counters_are_used_only_for_their_sources():
+    got = bench.measured_traffic("medium")
+    text = open(os.path.join(ROOT, "profiles", "traffic_medium.md")).read()
+    if f"`{bench.kernel_source_digest()}`" in text:
+        assert got is not None and got > 0
+        assert f"`{int(got)}`" in text
+    else:
+        assert got is None
+
+
+def test_traffic_is_null_for_other_sources(monkeypatch):
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0000000000000000")
+    assert bench.measured_traffic("medium") is None
+    assert bench.measured_traffic("no_such_workload") is None
+
+
+def test_host_info_fields():
+    h = bench.host_info()
+    assert set(h) == {"cpu_model", "logical_cpus", "usable_cpus"}
+    assert h["usable_cpus"] >= 1
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
