@@ -64,6 +64,9 @@ class OracleLib:
         lib.oracle_fault_sim.argtypes = [ctypes.c_int, P, U, P, U, U, P, U, P, P, U,
                                          ctypes.c_int, ctypes.c_int, P, P]
         lib.oracle_fault_sim.restype = ctypes.c_int
+        lib.oracle_fault_sim_ex.argtypes = [ctypes.c_int, P, U, P, U, U, P, U, P, P, U,
+                                            ctypes.c_int, ctypes.c_int, P, P, P, P]
+        lib.oracle_fault_sim_ex.restype = ctypes.c_int
         self.lib = lib
 
     def golden(self, design, stimulus: np.ndarray, T: int) -> np.ndarray:
@@ -95,6 +98,28 @@ class OracleLib:
         if rc:
             raise ValueError(f"oracle_fault_sim failed with {rc}")
         return detect, events
+
+    def fault_sim_stats(self, design, stimulus, T, faults, *, G=None, drop=True, variant=1, nthreads=None):
+        if G is None:
+            G = self.golden(design, stimulus, T)
+        nodes = np.ascontiguousarray(design.nodes)
+        po = np.ascontiguousarray(design.po, dtype=np.uint32)
+        stim = np.ascontiguousarray(stimulus[:T], dtype=np.uint64)
+        G = np.ascontiguousarray(G[:T], dtype=np.uint64)
+        fl = np.ascontiguousarray(faults)
+        F = fl.size
+        detect = np.empty(F, dtype=np.uint32)
+        events = np.empty(F, dtype=np.uint64)
+        words = np.empty(F, dtype=np.uint64)
+        lastreg = np.empty(F, dtype=np.uint32)
+        nt = default_threads() if nthreads is None else nthreads
+        rc = self.lib.oracle_fault_sim_ex(variant, _ptr(nodes), nodes.size, _ptr(po), po.size,
+                                          design.num_pi, _ptr(stim), T, _ptr(G), _ptr(fl), F,
+                                          1 if drop else 0, nt, _ptr(detect), _ptr(events), _ptr(words),
+                                          _ptr(lastreg))
+        if rc:
+            raise ValueError(f"oracle_fault_sim_ex failed with {rc}")
+        return detect, events, words, lastreg
 
 
 def _load() -> OracleLib:
@@ -133,6 +158,18 @@ def fault_sim(design, stimulus: np.ndarray, T: int, faults: np.ndarray, *, G: np
     """
     return _load().fault_sim(design, stimulus, T, faults, G=G, drop=drop, variant=variant,
                              nthreads=nthreads)
+
+
+def fault_sim_stats(design, stimulus: np.ndarray, T: int, faults: np.ndarray, *, G: np.ndarray | None = None,
+                    drop: bool = True, variant: int = 1, nthreads: int | None = None):
+    """fault_sim plus two statistics per fault: the algorithmic memory words of
+    the byte model (w(site) per simulated cycle, (k + 2) w(n) per event at a
+    node with k operands, 2 w(r) more per divergent register and cycle; w = 2
+    words for nodes wider than 32 bits, else 1), and the last cycle in which
+    some register's state diverges (0xFFFFFFFF if none).  Returns
+    (detect, events, words, lastreg)."""
+    return _load().fault_sim_stats(design, stimulus, T, faults, G=G, drop=drop, variant=variant,
+                                   nthreads=nthreads)
 
 
 def fault_cycles(detect: np.ndarray, T: int) -> int:

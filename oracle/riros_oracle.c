@@ -38,6 +38,18 @@
  *     i.e. its D one cycle earlier) or its own faulty value is divergent.
  *     With dropping, events stop after the detect cycle (that cycle included);
  *     without, they run to the last cycle.  detect does not depend on drop.
+ *   - statistics (optional outputs, for the benchmark's byte model and the
+ *     workload calibration; they change no result):
+ *       words    the algorithmic memory words the method must touch, with
+ *                w(n) = 2 for a node wider than 32 bits, else 1: per
+ *                simulated cycle w(site) (the site's golden word, read to see
+ *                whether the fault is excited); per event at node n,
+ *                (k + 2) * w(n), k = operand count of a combinational node
+ *                (0 otherwise): its operands, its own golden word and its
+ *                faulty value; per register whose state diverges, 2 * w(r)
+ *                more (the divergent state is read and written);
+ *       lastreg  the last cycle in which some register's state diverges
+ *                (0xFFFFFFFF if none), within the simulated cycles.
  *
  * Parity pins: tests/test_oracle_*.py (closed forms, brute force against a
  * bit-blasted evaluator, invariants, O0 against O1).
@@ -113,6 +125,16 @@ static uint64_t o_force(uint64_t v, const o_fault* f, uint32_t t)
     uint64_t bit = 1ull << f->bit;
     if (f->stuck == O_FLIP) return t == f->t0 ? (v ^ bit) : v;
     return f->stuck ? (v | bit) : (v & ~bit);
+}
+
+/* Words of a node's value: two for a node wider than 32 bits. */
+static uint64_t o_ww(const o_node* x) { return x->width > 32 ? 2u : 1u; }
+
+/* Words of one event at node x (operands, golden word, faulty value). */
+static uint64_t o_event_words(const o_node* x)
+{
+    uint64_t k = o_is_comb(x->op) ? (uint64_t)o_arity[x->op] : 0u;
+    return (k + 2u) * o_ww(x);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -251,13 +273,13 @@ typedef struct {
 
 static void o0_one(const o_design* d, const uint64_t* stim, uint32_t T, const uint64_t* G,
                    const o_fault* f, int drop, o0_scratch* s, uint32_t* detect_out,
-                   uint64_t* events_out)
+                   uint64_t* events_out, uint64_t* words_out, uint32_t* lastreg_out)
 {
     const uint32_t N = d->N;
     uint64_t* val = s->val;
     uint64_t* state = s->state;
-    uint32_t detect = O_UNDET;
-    uint64_t ev = 0;
+    uint32_t detect = O_UNDET, lastreg = O_UNDET, cycles = 0;
+    uint64_t ev = 0, words = 0;
     for (uint32_t i = 0; i < d->nregs; ++i) {
         uint32_t r = d->regs[i];
         state[r] = d->nd[r].param & o_mask(d->nd[r].width);
@@ -271,16 +293,18 @@ static void o0_one(const o_design* d, const uint64_t* stim, uint32_t T, const ui
             if (n == f->site) v = o_force(v, f, t);
             val[n] = v;
         }
+        cycles = t + 1;
         for (uint32_t n = 0; n < N; ++n) {
             const o_node* x = &d->nd[n];
             int div_in = 0;
             if (x->op == O_REG) {
                 div_in = state[n] != g[n];
-            } else {
+                if (div_in) { words += 2u * o_ww(x); lastreg = t; }
+            } else if (o_is_comb(x->op)) {
                 for (int k = 0; k < o_arity[x->op]; ++k)
                     div_in |= val[x->in[k]] != g[x->in[k]];
             }
-            if (div_in || val[n] != g[n]) ev++;
+            if (div_in || val[n] != g[n]) { ev++; words += o_event_words(x); }
         }
         for (uint32_t i = 0; i < d->npo; ++i)
             if (val[d->po[i]] != g[d->po[i]] && detect == O_UNDET) detect = t;
@@ -292,6 +316,8 @@ static void o0_one(const o_design* d, const uint64_t* stim, uint32_t T, const ui
     }
     *detect_out = detect;
     if (events_out) *events_out = ev;
+    if (words_out) *words_out = words + (uint64_t)cycles * o_ww(&d->nd[f->site]);
+    if (lastreg_out) *lastreg_out = lastreg;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -382,11 +408,11 @@ typedef struct {
 
 static void o1_one(const o_design* d, const o1_graph* gr, const uint64_t* stim, uint32_t T,
                    const uint64_t* G, const o_fault* f, int drop, o1_scratch* s,
-                   uint32_t* detect_out, uint64_t* events_out)
+                   uint32_t* detect_out, uint64_t* events_out, uint64_t* words_out, uint32_t* lastreg_out)
 {
     const uint32_t N = d->N;
-    uint32_t detect = O_UNDET;
-    uint64_t ev = 0;
+    uint32_t detect = O_UNDET, lastreg = O_UNDET, cycles = 0;
+    uint64_t ev = 0, words = 0;
     uint32_t nnext = 0;
     /* stamps are cycle+1 offset by a per-call base so that scratch need not be cleared */
     for (uint32_t t = 0; t < T; ++t) {
@@ -403,11 +429,14 @@ static void o1_one(const o_design* d, const o1_graph* gr, const uint64_t* stim, 
             s->bucket[s->boff[_l] + s->bfill[_l]++] = _n;                          \
         }                                                                          \
     } while (0)
+        cycles = t + 1;
         /* registers whose D diverged in the previous cycle */
         for (uint32_t i = 0; i < nnext; ++i) {
             uint32_t r = s->rnext[i];
             s->rstate[r] = s->rnextv[i];
             s->rstamp[r] = stamp;
+            words += 2u * o_ww(&d->nd[r]);
+            lastreg = t;
             O1_PUSH(r);
         }
         nnext = 0;
@@ -436,7 +465,7 @@ static void o1_one(const o_design* d, const o1_graph* gr, const uint64_t* stim, 
                 }
                 if (n == f->site) v = o_force(v, f, t);
                 int div_out = v != g[n];
-                if (div_in || div_out) ev++;
+                if (div_in || div_out) { ev++; words += o_event_words(x); }
                 if (!div_out) continue;
                 s->fval[n] = v;
                 s->fstamp[n] = stamp;
@@ -455,6 +484,8 @@ static void o1_one(const o_design* d, const o1_graph* gr, const uint64_t* stim, 
     }
     *detect_out = detect;
     if (events_out) *events_out = ev;
+    if (words_out) *words_out = words + (uint64_t)cycles * o_ww(&d->nd[f->site]);
+    if (lastreg_out) *lastreg_out = lastreg;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -473,6 +504,8 @@ typedef struct {
     int drop;
     uint32_t* detect;
     uint64_t* events;
+    uint64_t* words;
+    uint32_t* lastreg;
     atomic_uint next;
     atomic_int failed;
 } o_job;
@@ -491,7 +524,8 @@ static void* o_worker(void* arg)
             uint32_t i = atomic_fetch_add(&j->next, 1u);
             if (i >= j->F) break;
             o0_one(j->d, j->stim, j->T, j->G, &j->faults[i], j->drop, &s, &j->detect[i],
-                   j->events ? &j->events[i] : NULL);
+                   j->events ? &j->events[i] : NULL, j->words ? &j->words[i] : NULL,
+                   j->lastreg ? &j->lastreg[i] : NULL);
         }
         free(s.val); free(s.state);
     } else {
@@ -522,7 +556,8 @@ static void* o_worker(void* arg)
                 memset(s.qstamp, 0, n1 * sizeof(uint32_t));
                 memset(s.rstamp, 0, n1 * sizeof(uint32_t));
                 o1_one(j->d, gr, j->stim, j->T, j->G, &j->faults[i], j->drop, &s, &j->detect[i],
-                       j->events ? &j->events[i] : NULL);
+                       j->events ? &j->events[i] : NULL, j->words ? &j->words[i] : NULL,
+                       j->lastreg ? &j->lastreg[i] : NULL);
             }
         }
         free(s.fval); free(s.fstamp); free(s.qstamp); free(s.rstate); free(s.rstamp);
@@ -533,14 +568,15 @@ static void* o_worker(void* arg)
 
 /*
  * Fault simulation of F faults.  variant 0 = O0, 1 = O1.  G is the golden trace
- * from oracle_golden.  detect[F] and events[F] (may be NULL) are written.
- * nthreads <= 0 means 1.  Returns 0, or a negative code for an invalid design
- * (-1), a combinational cycle (-2), memory (-3) or an invalid fault (-4).
+ * from oracle_golden.  detect[F] and events[F], words[F] and lastreg[F] (the
+ * last three may be NULL) are written.  nthreads <= 0 means 1.  Returns 0, or
+ * a negative code for an invalid design (-1), a combinational cycle (-2),
+ * memory (-3) or an invalid fault (-4).
  */
-int oracle_fault_sim(int variant, const void* nodes, uint32_t N, const uint32_t* po, uint32_t npo,
-                     uint32_t npi, const uint64_t* stim, uint32_t T, const uint64_t* G,
-                     const void* faults, uint32_t F, int drop, int nthreads, uint32_t* detect,
-                     uint64_t* events)
+int oracle_fault_sim_ex(int variant, const void* nodes, uint32_t N, const uint32_t* po, uint32_t npo,
+                        uint32_t npi, const uint64_t* stim, uint32_t T, const uint64_t* G,
+                        const void* faults, uint32_t F, int drop, int nthreads, uint32_t* detect,
+                        uint64_t* events, uint64_t* words, uint32_t* lastreg)
 {
     o_design d;
     int rc = o_prepare(&d, nodes, N, po, npo, npi);
@@ -556,7 +592,7 @@ int oracle_fault_sim(int variant, const void* nodes, uint32_t N, const uint32_t*
     if (variant == 1 && (rc = o1_build(&d, &gr)) != 0) { o1_free(&gr); o_release(&d); return rc; }
     o_job j;
     j.variant = variant; j.d = &d; j.gr = &gr; j.stim = stim; j.T = T; j.G = G; j.faults = fl;
-    j.F = F; j.drop = drop; j.detect = detect; j.events = events;
+    j.F = F; j.drop = drop; j.detect = detect; j.events = events; j.words = words; j.lastreg = lastreg;
     atomic_init(&j.next, 0u);
     atomic_init(&j.failed, 0);
     if (nthreads < 1) nthreads = 1;
@@ -570,4 +606,14 @@ int oracle_fault_sim(int variant, const void* nodes, uint32_t N, const uint32_t*
     if (variant == 1) o1_free(&gr);
     o_release(&d);
     return atomic_load(&j.failed) ? -3 : 0;
+}
+
+/* detect and events only. */
+int oracle_fault_sim(int variant, const void* nodes, uint32_t N, const uint32_t* po, uint32_t npo,
+                     uint32_t npi, const uint64_t* stim, uint32_t T, const uint64_t* G,
+                     const void* faults, uint32_t F, int drop, int nthreads, uint32_t* detect,
+                     uint64_t* events)
+{
+    return oracle_fault_sim_ex(variant, nodes, N, po, npo, npi, stim, T, G, faults, F, drop, nthreads,
+                               detect, events, NULL, NULL);
 }

@@ -195,3 +195,47 @@ def test_delay_line_flip(variant):
         assert det[i] == (want if want < T else UND), (j, b, t0)
         # one divergent node per cycle from t0 through the last stage reached
         assert ev[i] == min(L - j, T - 1 - t0) + 1, (j, b, t0)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n", [8, 32, 33, 64])
+def test_counter_words_closed_form(variant, n):
+    """SA1 on a counter register bit, output = the register: detected in cycle
+    0, where the register (excited site, no operands) and the adder (two
+    operands) are the only events: 2w + 4w words, plus w for the site's golden
+    word; w = 2 words for values wider than 32 bits.  No register state has
+    diverged by then."""
+    T = 50
+    d, cnt, add, _ = counter(n)
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    fl = faults([(cnt, k, 1) for k in (0, n // 2, n - 1)])
+    det, ev, words, lastreg = oracle.fault_sim_stats(d, stim, T, fl, variant=variant)
+    w = 2 if n > 32 else 1
+    np.testing.assert_array_equal(det, 0)
+    np.testing.assert_array_equal(ev, 2)
+    np.testing.assert_array_equal(words, 7 * w)
+    np.testing.assert_array_equal(lastreg, UND)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("w_bits", [8, 32, 40, 64])
+def test_delay_line_words_closed_form(variant, w_bits):
+    """SA1 on bit 0 of the input of an L-stage delay line fed with zeros: the
+    input is excited every cycle, stage j holds the divergence from cycle j on,
+    the output (stage L) shows it in cycle L.  Per cycle t <= L: the site's
+    word w, the input event 2w, and min(t, L) divergent registers at 4w each
+    (event 2w, state read and write 2w); the last divergent register cycle is
+    L."""
+    L, T = 5, 40
+    d, x, regs = delay_line(L, w_bits)
+    stim = np.zeros((T, 1), dtype=np.uint64)
+    fl = faults([(x, 0, 1)])
+    w = 2 if w_bits > 32 else 1
+    for drop in (True, False):
+        det, ev, words, lastreg = oracle.fault_sim_stats(d, stim, T, fl, drop=drop, variant=variant)
+        last = L if drop else T - 1
+        ts = np.arange(last + 1)
+        assert det[0] == L
+        assert ev[0] == int((1 + np.minimum(ts, L)).sum())
+        assert words[0] == int((3 * w + 4 * w * np.minimum(ts, L)).sum())
+        assert lastreg[0] == last

@@ -28,7 +28,11 @@ MUTANTS = {
                        "if (val[d->po[i]] != g[d->po[i]] && detect == O_UNDET) detect = t + 1;"),
     "o1_no_register_fanout": ("s->rnext[nnext] = r;\n                    s->rnextv[nnext] = v & o_mask(d->nd[r].width);\n                    nnext++;",
                               "(void)r;"),
-    "o1_output_divergence_not_counted": ("if (div_in || div_out) ev++;", "if (div_in) ev++;"),
+    "o1_output_divergence_not_counted": ("if (div_in || div_out) { ev++; words += o_event_words(x); }",
+                                         "if (div_in) { ev++; words += o_event_words(x); }"),
+    "o1_register_words_dropped": ("            words += 2u * o_ww(&d->nd[r]);\n", ""),
+    "wide_words_not_doubled": ("return x->width > 32 ? 2u : 1u;", "return 1u;"),
+    "event_words_without_operands": ("return (k + 2u) * o_ww(x);", "return 2u * o_ww(x);"),
     "shr_is_shl": ("case O_SHR: r = k >= 64 ? 0 : (a >> k);", "case O_SHR: r = k >= 64 ? 0 : (a << k);"),
     "mul_is_add": ("case O_MUL: r = a * b;", "case O_MUL: r = a + b;"),
     "flip_one_cycle_late": ("return t == f->t0 ? (v ^ bit) : v;", "return t == f->t0 + 1u ? (v ^ bit) : v;"),
@@ -72,6 +76,17 @@ def _brute_pass(lib) -> bool:
                     for i in range(fl.size):
                         if det[i] != ref[i][0][j] or ev[i] != ref[i][1][j]:
                             return False
+    # byte-model words and the last divergent-register cycle, on one design
+    d = tiny_designs()[4]
+    fl = np.concatenate([all_faults(d), all_flip_faults(d, T)])
+    for drop in (True, False):
+        ref = [reference_counts(d, seqs, fault_tuple(f), drop, stats=True) for f in fl]
+        for j in range(seqs.shape[0]):
+            for variant in (0, 1):
+                _, _, words, lastreg = lib.fault_sim_stats(d, seqs[j], T, fl, drop=drop, variant=variant)
+                for i in range(fl.size):
+                    if words[i] != ref[i][2][j] or lastreg[i] != ref[i][3][j]:
+                        return False
     return True
 
 
@@ -93,6 +108,17 @@ def _counter_pass(lib) -> bool:
         det, _ = lib.fault_sim(d, stim, T, fl, variant=variant)
         want = [2 ** k if 2 ** k < T else oracle.UNDETECTED for k in range(8)]
         if list(det) != want:
+            return False
+    # a 64-bit counter, SA1 on a register bit: 7 words of two halves each
+    b = Builder()
+    b.pi(1)
+    cnt = b.reg(64)
+    add = b.node(ADD, 64, (cnt, b.const(64, 1)))
+    b.set_d(cnt, add)
+    d = b.design([cnt])
+    for variant in (0, 1):
+        _, _, words, _ = lib.fault_sim_stats(d, stim[:20], 20, faults([(cnt, 5, 1)]), variant=variant)
+        if int(words[0]) != 14:
             return False
     return True
 
