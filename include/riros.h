@@ -169,6 +169,15 @@ typedef struct {
                               waves_per_cu wavefronts resident despite the
                               structural LDS of the design, else 4 */
     void* stream;
+    uint64_t* words;       /* optional per-fault output [F] (same memory space as detect):
+                              the memory words the method must touch for the fault
+                              (the byte model of the measurement): per simulated cycle
+                              the site's golden word; per event at a node with k
+                              operands (k = 0 for a register, input or constant),
+                              k + 2 words (operands, the node's golden word, its
+                              faulty value); a register whose state diverges, 2 words
+                              more (state read and written); every word counts twice
+                              for a node wider than 32 bits.  4 bytes a word. */
 } riros_sim_opts;
 
 typedef struct {
@@ -176,6 +185,7 @@ typedef struct {
     uint64_t total;         /* faults simulated */
     uint64_t fault_cycles;  /* sum over faults of (detect + 1), or T if undetected */
     uint64_t events;        /* sum of per-fault event counts */
+    uint64_t words;         /* sum of per-fault byte-model words (riros_sim_opts.words) */
 } riros_coverage;
 
 /* Fault-simulate F single faults (stuck-at or bit flip) against the golden trace.
@@ -272,8 +282,10 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
 int riros_batch_launch(riros_batch b, void* stream);
 
 /* Results of design i after the last launch (waits for it): detect[F[i]],
- * events[F[i]] (may be NULL), coverage (may be NULL); host arrays. */
-int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, riros_coverage* cov);
+ * events[F[i]] and words[F[i]] (byte-model words as in riros_sim_opts.words;
+ * both may be NULL), coverage (may be NULL); host arrays. */
+int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, uint64_t* words,
+                     riros_coverage* cov);
 
 void riros_batch_free(riros_batch b);
 
@@ -286,6 +298,24 @@ int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels,
 int riros_last_kernel_ms(float* ms);
 
 const char* riros_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Peak-rate probes for the roofline (measurement tools, not part of the      */
+/* method): the rates a fault-simulation pass is compared against, measured   */
+/* on the current device.                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* HBM streaming rate: the best of `reps` device copies of `bytes` bytes (each
+ * reads `bytes` and writes `bytes`), *gbs = 2 * bytes / time in GB/s.  Takes
+ * 2 * bytes of device memory for the call.  Returns 0, -1 (bad argument), -3
+ * (no memory) or -4 (HIP error). */
+int riros_peak_hbm(uint64_t bytes, int reps, double* gbs, void* stream);
+
+/* int32 vector-ALU rate: the best of `reps` launches of independent chains of
+ * single-cycle integer instructions (v_add_u32, v_xor_b32) on every compute
+ * unit, *ops_per_s = instructions per second counted per lane.  Returns 0,
+ * -1, -3 or -4 as above. */
+int riros_peak_valu(int reps, double* ops_per_s, void* stream);
 
 #ifdef __cplusplus
 }

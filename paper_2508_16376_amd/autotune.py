@@ -9,10 +9,12 @@ workspace, and (with a predictor) the
 predicted-load quantile above which faults start on the structural path.  The paper fixes its overload threshold
 by hand (Sec. V-A); here candidates are timed and the fastest kept, one
 parameter at a time (coordinate descent), with the result cached by design
-hash.  Candidates run on the whole fault list: a sample with fewer faults than
-lanes would hide the contention of the structural path (one fault per
-wavefront) and pick thresholds that fail at full scale.  No parameter changes
-a result, only time.
+hash.  Candidates run on a seeded sample of the fault list (by default the
+whole list): the sample must keep more faults than the chip has lanes, or it
+would hide the contention of the structural path (one fault per wavefront)
+and pick thresholds that fail at full scale.  A wall-clock budget bounds the
+search: once it is spent the best point so far is confirmed and kept.  No
+parameter changes a result, only time.
 """
 from __future__ import annotations
 
@@ -20,6 +22,7 @@ import hashlib
 import json
 import math
 import os
+import time
 
 import numpy as np
 
@@ -67,10 +70,13 @@ def _time_single(d, g, faults, priority, p, reps=2):
 
 
 class Autotuner:
-    def __init__(self, cache_path: str | None = None, progress=None):
+    def __init__(self, cache_path: str | None = None, progress=None, budget_s: float | None = None):
         """progress: optional callable taking one line of text per timed
-        point (a long tuning run then reports as it goes)."""
+        point (a long tuning run then reports as it goes).  budget_s: wall
+        time after which no new point is timed (the confirmation of the best
+        points still runs)."""
         self.progress = progress
+        self.budget_s = budget_s
         self.cache_path = cache_path
         self.cache: dict[str, dict] = {}
         if cache_path and os.path.exists(cache_path):
@@ -84,6 +90,11 @@ class Autotuner:
                 json.dump(self.cache, f, indent=1, sort_keys=True)
 
     def _descend(self, measure, with_priority: bool, confirm: int = 3):
+        t_start = time.perf_counter()
+
+        def spent():
+            return self.budget_s is not None and time.perf_counter() - t_start > self.budget_s
+
         best = dict(DEFAULT)
         best_t = measure(best)
         self.log.append({"params": dict(best), "ms": best_t})
@@ -101,7 +112,7 @@ class Autotuner:
                     cand = dict(best)
                     cand[name] = v
                     key = tuple(sorted(cand.items(), key=lambda kv: kv[0]))
-                    if key in seen:
+                    if key in seen or spent():
                         continue
                     seen.add(key)
                     t = measure(cand)
@@ -111,7 +122,7 @@ class Autotuner:
                         self.progress(f"[autotune] {cand} {t:.3f} ms")
                     if t < best_t:
                         best, best_t = cand, t
-            if best == start:
+            if best == start or spent():
                 break
         # The fastest few points are timed twice more and ranked by their
         # mean: a single lucky timing should not pick the schedule.
@@ -126,11 +137,17 @@ class Autotuner:
             _, best_t, best = min(scored, key=lambda x: x[0])
         return best, best_t
 
-    def tune_single(self, design_np, d, g, faults, priority=None, T=None):
-        """Parameters for riros_fault_sim(mode=TWO_D) on this design and fault list."""
+    def tune_single(self, design_np, d, g, faults, priority=None, T=None, sample=None):
+        """Parameters for riros_fault_sim(mode=TWO_D) on this design and fault
+        list.  sample: time the candidates on these fault indexes only."""
         key = design_key(design_np, T or 0, faults.size, priority is not None)
+        if sample is not None:
+            key += f"-s{len(sample)}"
         if key in self.cache:
             return self.cache[key]["params"]
+        if sample is not None:
+            faults = np.ascontiguousarray(faults[sample])
+            priority = None if priority is None else priority[sample]
         ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
         best, t = self._descend(lambda p: _time_single(d, g, faults, ps, p), priority is not None)
         self.cache[key] = {"params": best, "ms": t}

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libriros.so")
-SOURCES = ["design.cpp", "kernels_plain.hip", "twod.hip", "concurrent.hip", "kernels_mlp.hip", "riros_abi.hip"]
+SOURCES = ["design.cpp", "kernels_plain.hip", "twod.hip", "concurrent.hip", "kernels_mlp.hip", "riros_abi.hip",
+           "peaks.hip"]
 ARCH = os.environ.get("RIROS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(64) k_concurrent(DevDesign d, const uint64_t* 
                                                    const riros_fault* __restrict__ faults,
                                                    const uint32_t* __restrict__ order, uint32_t F, int drop,
                                                    ConcState st, uint32_t* __restrict__ detect,
-                                                   uint64_t* __restrict__ events)
+                                                   uint64_t* __restrict__ events, uint64_t* __restrict__ words)
 {
     extern __shared__ uint64_t conc_lds[];
     const uint32_t N = d.N, R = d.R;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(64) k_concurrent(DevDesign d, const uint64_t* 
             srow = Bp + (size_t)(d.bp_off[site] + fbit) * TW;
         }
         uint32_t det = RIROS_UNDETECTED;
-        uint64_t ev = 0;
+        uint64_t ev = 0, wk = 0;   // events and byte-model words of the lane's fault
         bool rpend = false;   // registers were scheduled for the next cycle (uniform)
         for (uint32_t i = lane; i < RW; i += 64) rn[i] = 0;
         lds_order();
@@ -240,6 +240,8 @@ __global__ void __launch_bounds__(64) k_concurrent(DevDesign d, const uint64_t* 
                         const bool dout = active && v != gv;
                         din = din && active;
                         ev += (din || dout) ? 1u : 0u;
+                        const uint32_t ew = (din || dout) ? (uint32_t)x.words : 0u;
+                        wk += (isreg && din) ? 2u * ew : ew;
                         const uint64_t dm = __ballot(dout);
                         if (dm == 0) continue;
                         val[(size_t)n * 64 + lane] = v;
@@ -285,6 +287,8 @@ __global__ void __launch_bounds__(64) k_concurrent(DevDesign d, const uint64_t* 
         if (pos < F) {
             detect[fi] = det;
             if (events) events[fi] = ev;
+            const uint64_t cycles = (drop && det != RIROS_UNDETECTED) ? (uint64_t)det + 1u : (uint64_t)T;
+            words[fi] = wk + cycles * (d.uwidth[faults[fi].site] > 32 ? 2u : 1u);
         }
         base += (uint64_t)T + 1;
     }
@@ -342,6 +346,7 @@ size_t conc_slot_bytes(uint32_t N, uint32_t R)
 
 int run_concurrent(const DevDesign& d, ConcWorkspace& ws, const GoldenView& gv, const riros_fault* faults,
                    uint32_t F, int drop, int waves_per_cu, int num_cu, uint32_t* detect, uint64_t* events,
+                   uint64_t* words,
                    hipEvent_t ev0, hipEvent_t ev1, hipStream_t s, std::string& err)
 {
     const size_t lds = conc_lds_bytes(d.N, d.R);
@@ -429,7 +434,7 @@ int run_concurrent(const DevDesign& d, ConcWorkspace& ws, const GoldenView& gv, 
         return RIROS_EDEVICE;
     }
     hipLaunchKernelGGL(k_concurrent, dim3(slots), dim3(64), lds, s, d, gv.Gn, gv.Bp, gv.T, gv.TW, faults,
-                       (const uint32_t*)order, F, drop, st, detect, events);
+                       (const uint32_t*)order, F, drop, st, detect, events, words);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) { err = std::string("concurrent kernel: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }

@@ -41,6 +41,7 @@ constexpr size_t kConcMaxSimBytes = 128ull << 30;
 // the faulty-state budget allow).  ev0/ev1 bracket the sort and the kernel.
 int run_concurrent(const DevDesign& d, ConcWorkspace& ws, const GoldenView& gv, const riros_fault* faults,
                    uint32_t F, int drop, int waves_per_cu, int num_cu, uint32_t* detect, uint64_t* events,
+                   uint64_t* words,
                    hipEvent_t ev0, hipEvent_t ev1, hipStream_t s, std::string& err);
 
 }  // namespace riros

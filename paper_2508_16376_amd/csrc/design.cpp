@@ -14,6 +14,12 @@
 
 namespace riros {
 
+uint8_t event_words(uint8_t op, uint8_t width)
+{
+    const uint32_t k = op_is_comb(op) ? (uint32_t)op_arity(op) : 0u;
+    return (uint8_t)((k + 2u) * (width > 32 ? 2u : 1u));
+}
+
 int op_arity(uint8_t op)
 {
     switch (op) {
@@ -228,6 +234,7 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
         r.fo1 = img.fo_off[i + 1];
         r.rfo0 = img.rfo_off[i];
         r.rfo1 = img.rfo_off[i + 1];
+        r.words = event_words(o.op, o.width);
         img.bp_off[i] = rows;
         rows += o.width;
     }

@@ -29,9 +29,11 @@ constexpr uint32_t kFanoutPad = 4;
 
 // 32-byte node record for per-lane walks: the descriptor plus the node's
 // fan-out ranges, so one load gives everything needed to evaluate a node and
-// schedule its users.
+// schedule its users.  `words` is the node's share of the byte model (memory
+// words an evaluation of the node must touch, counted per event; see
+// event_words).
 struct NodeRec {
-    uint8_t op, width, flags, pad;
+    uint8_t op, width, flags, words;
     uint32_t a, b, c;
     uint32_t fo0, fo1;     // combinational users: fo[fo0..fo1)
     uint32_t rfo0, rfo1;   // registers fed: rfo[rfo0..rfo1)
@@ -66,6 +68,14 @@ void node_features(const Image& img, std::vector<float>& out /* [N][4] */);
 int build_image(const riros_design_desc& desc, Image& img, std::string& err);
 
 int op_arity(uint8_t op);
+// Algorithmic memory words of one event at a node (the byte model of the
+// fault-simulation pass): its k operands (k = 0 for registers, inputs and
+// constants), its own golden word and its faulty value, each two words when
+// the node is wider than 32 bits.  A register whose state diverges moves its
+// state too (read and written): twice this for a register event with a
+// divergent state.  Per simulated cycle the site's golden word (1 or 2 words)
+// is added once per fault.
+uint8_t event_words(uint8_t op, uint8_t width);
 bool op_is_comb(uint8_t op);
 
 }  // namespace riros

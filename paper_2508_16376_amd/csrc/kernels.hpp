@@ -68,12 +68,12 @@ size_t plain_lds_bytes(const DevDesign& d, uint32_t wpp);
 hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t wpp, uint32_t* detect, uint64_t* events,
-                              hipStream_t s);
+                              uint64_t* words, hipStream_t s);
 
 hipError_t launch_validate_faults(const DevDesign& d, const riros_fault* faults, uint32_t F,
                                   uint32_t* bad_count, hipStream_t s);
 
-hipError_t launch_coverage(const uint32_t* detect, const uint64_t* events, uint32_t F, uint32_t T,
-                           riros_coverage* cov, hipStream_t s);
+hipError_t launch_coverage(const uint32_t* detect, const uint64_t* events, const uint64_t* words, uint32_t F,
+                           uint32_t T, riros_coverage* cov, hipStream_t s);
 
 }  // namespace riros

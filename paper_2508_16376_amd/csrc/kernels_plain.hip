@@ -114,7 +114,8 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
                                                     const riros_fault* __restrict__ faults,
                                                     uint32_t F, int drop, PlainWorkspace ws, uint32_t wpp,
                                                     uint32_t* __restrict__ detect_out,
-                                                    uint64_t* __restrict__ events_out)
+                                                    uint64_t* __restrict__ events_out,
+                                                    uint64_t* __restrict__ words_out)
 {
     extern __shared__ uint32_t lds[];
     const WaveLds s = wave_lds_carve(lds, d.N, d.L, d.R, wpp);
@@ -125,11 +126,12 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
     uint64_t stamp0 = *ws.stamp_dev;
     for (uint32_t fi = blockIdx.x; fi < F; fi += gridDim.x) {
         uint32_t det;
-        uint64_t ev;
-        wave_sim_fault(d, Gr, Gn, Bp, T, TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        uint64_t ev, wk;
+        wave_sim_fault(d, Gr, Gn, Bp, T, TW, faults[fi], drop, s, slots, regs, stamp0, det, ev, wk);
         if (threadIdx.x == 0) {
             detect_out[fi] = det;
             if (events_out) events_out[fi] = ev;
+            words_out[fi] = wk;
         }
     }
 }
@@ -148,14 +150,14 @@ hipError_t launch_advance_stamp(uint64_t* stamp_dev, uint64_t by, hipStream_t s)
 hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
                               const riros_fault* faults, uint32_t F, int drop, uint32_t blocks,
                               const PlainWorkspace& ws, uint32_t wpp, uint32_t* detect, uint64_t* events,
-                              hipStream_t s)
+                              uint64_t* words, hipStream_t s)
 {
     const size_t lds = plain_lds_bytes(d, wpp);
     hipError_t e = hipFuncSetAttribute((const void*)k_fault_plain,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fault_plain, dim3(blocks), dim3(64), lds, s, d, g.G, g.Gn, g.Bp, g.T, g.TW, faults, F, drop, ws,
-                       wpp, detect, events);
+                       wpp, detect, events, words);
     return hipGetLastError();
 }
 
@@ -184,22 +186,26 @@ hipError_t launch_validate_faults(const DevDesign& d, const riros_fault* faults,
 }
 
 __global__ void k_coverage(const uint32_t* __restrict__ detect, const uint64_t* __restrict__ events,
-                           uint32_t F, uint32_t T, riros_coverage* __restrict__ cov)
+                           const uint64_t* __restrict__ words, uint32_t F, uint32_t T,
+                           riros_coverage* __restrict__ cov)
 {
-    uint64_t det = 0, fc = 0, ev = 0;
+    uint64_t det = 0, fc = 0, ev = 0, wk = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < F; i += gridDim.x * blockDim.x) {
         const uint32_t dc = detect[i];
         det += dc != RIROS_UNDETECTED;
         fc += dc != RIROS_UNDETECTED ? (uint64_t)dc + 1 : (uint64_t)T;
         if (events) ev += events[i];
+        wk += words[i];
     }
     det = wave_sum_u64(det);
     fc = wave_sum_u64(fc);
     ev = wave_sum_u64(ev);
+    wk = wave_sum_u64(wk);
     if (lane_id() == 0) {
         atomicAdd((unsigned long long*)&cov->detected, (unsigned long long)det);
         atomicAdd((unsigned long long*)&cov->fault_cycles, (unsigned long long)fc);
         atomicAdd((unsigned long long*)&cov->events, (unsigned long long)ev);
+        atomicAdd((unsigned long long*)&cov->words, (unsigned long long)wk);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)&cov->total, (unsigned long long)F);
 }
@@ -211,17 +217,18 @@ __global__ void k_zero_cov(riros_coverage* cov)
         cov->total = 0;
         cov->fault_cycles = 0;
         cov->events = 0;
+        cov->words = 0;
     }
 }
 
-hipError_t launch_coverage(const uint32_t* detect, const uint64_t* events, uint32_t F, uint32_t T,
-                           riros_coverage* cov, hipStream_t s)
+hipError_t launch_coverage(const uint32_t* detect, const uint64_t* events, const uint64_t* words, uint32_t F,
+                           uint32_t T, riros_coverage* cov, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_cov, dim3(1), dim3(64), 0, s, cov);
     uint32_t blocks = (F + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_coverage, dim3(blocks), dim3(256), 0, s, detect, events, F, T, cov);
+    hipLaunchKernelGGL(k_coverage, dim3(blocks), dim3(256), 0, s, detect, events, words, F, T, cov);
     return hipGetLastError();
 }
 

@@ -97,6 +97,8 @@ struct riros_design_s {
     uint64_t* ws_regs = nullptr;
     size_t ws_regs_cap = 0;
     uint64_t* stamp_dev = nullptr;   // slot stamps above this are unused (advanced on the device by every run)
+    uint64_t* ws_words = nullptr;    // per-fault byte-model words when the caller asks for none (grow-only)
+    size_t ws_words_cap = 0;
     // two-dimensional kernel workspace
     riros::TwoDWorkspace twod{};
     // concurrent (node-major) mode workspace
@@ -137,6 +139,7 @@ static void free_design_mem(riros_design d)
     if (d->d_cov) (void)hipFree(d->d_cov);
     if (d->d_bad) (void)hipFree(d->d_bad);
     if (d->d_nodefeat) (void)hipFree(d->d_nodefeat);
+    if (d->ws_words) (void)hipFree(d->ws_words);
     riros::twod_free(d->twod);
     riros::conc_free(d->conc);
 }
@@ -349,6 +352,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     const riros_fault* d_faults = faults;
     uint32_t* d_detect = detect;
     uint64_t* d_events = events;
+    uint64_t* d_words = opts->words;
     const float* d_prio = opts->priority;
     if (!on_dev) {
         for (uint32_t i = 0; i < F; ++i) {
@@ -361,20 +365,21 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
             }
         }
         if (F == 0) {
-            if (cov) *cov = riros_coverage{0, 0, 0, 0};
+            if (cov) *cov = riros_coverage{0, 0, 0, 0, 0};
             return RIROS_OK;
         }
         const size_t fb = (size_t)F * sizeof(riros_fault), db = (size_t)F * 4, eb = (size_t)F * 8,
                      pb = opts->priority ? (size_t)F * 4 : 0;
-        int rc = ensure_stage(d, fb + db + eb + pb + 256);
+        int rc = ensure_stage(d, fb + db + 2 * eb + pb + 256);
         if (rc) return rc;
         char* base = (char*)d->stage;
         d_faults = (const riros_fault*)base;
         d_detect = (uint32_t*)(base + fb);
         d_events = (uint64_t*)(base + fb + db + (8 - (fb + db) % 8) % 8);
+        d_words = d_events + F;
         HIP_TRY(hipMemcpyAsync((void*)d_faults, faults, fb, hipMemcpyHostToDevice, s), "fault upload");
         if (opts->priority) {
-            float* dp = (float*)((char*)d_events + eb);
+            float* dp = (float*)((char*)d_words + eb);
             HIP_TRY(hipMemcpyAsync(dp, opts->priority, pb, hipMemcpyHostToDevice, s), "priority upload");
             d_prio = dp;
         }
@@ -389,6 +394,16 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         HIP_TRY(hipMemcpyAsync(&bad, d->d_bad, sizeof bad, hipMemcpyDeviceToHost, s), "validate read");
         HIP_TRY(hipStreamSynchronize(s), "validate sync");
         if (bad) return set_err(RIROS_EINVAL, std::to_string(bad) + " invalid faults in device fault list");
+        if (!d_words) {
+            if (d->ws_words_cap < F) {
+                if (d->ws_words) (void)hipFree(d->ws_words);
+                d->ws_words = nullptr;
+                d->ws_words_cap = 0;
+                HIP_TRY(hipMalloc((void**)&d->ws_words, (size_t)F * sizeof(uint64_t)), "words allocation");
+                d->ws_words_cap = F;
+            }
+            d_words = d->ws_words;
+        }
     }
 
     if (opts->mode == RIROS_MODE_PLAIN) {
@@ -408,14 +423,15 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         riros::PlainWorkspace ws{d->ws_slots, d->ws_regs, d->stamp_dev};
         HIP_TRY(hipEventRecord(g_ev0, s), "event record");
         HIP_TRY(riros::launch_fault_plain(d->dev, g->view(), d_faults, F, opts->drop ? 1 : 0, blocks, ws, wpp,
-                                          d_detect, d_events, s),
+                                          d_detect, d_events, d_words, s),
                 "plain fault kernel");
         HIP_TRY(hipEventRecord(g_ev1, s), "event record");
         HIP_TRY(riros::launch_advance_stamp(d->stamp_dev, per_block * T + 1, s), "stamp advance");
     } else if (opts->mode == RIROS_MODE_CONCURRENT) {
         std::string err;
         const int rc = riros::run_concurrent(d->dev, d->conc, g->view(), d_faults, F, opts->drop ? 1 : 0,
-                                             opts->waves_per_cu, d->num_cu, d_detect, d_events, g_ev0, g_ev1, s, err);
+                                             opts->waves_per_cu, d->num_cu, d_detect, d_events, d_words, g_ev0,
+                                             g_ev1, s, err);
         if (rc) return set_err(rc, err);
     } else {
         if (riros::plain_lds_bytes(d->dev, riros::kWordsNarrow) > 160 * 1024)
@@ -438,7 +454,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.num_cu = d->num_cu;
         std::string err;
         rc = riros::run_twod(d->dev, d->twod, g->view(), d_faults, d_prio, F, opts->drop ? 1 : 0, p, hws,
-                             heavy_blocks, d_detect, d_events, g_ev0, g_ev1, s, err);
+                             heavy_blocks, d_detect, d_events, d_words, g_ev0, g_ev1, s, err);
         if (rc) return set_err(rc, err);
     }
     g_ev_valid = true;
@@ -449,11 +465,14 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         if (rc) return set_err(rc, err);
     }
     riros_coverage* cov_dst = on_dev ? cov : d->d_cov;
-    if (cov) HIP_TRY(riros::launch_coverage(d_detect, d_events, F, T, cov_dst, s), "coverage");
+    if (cov) HIP_TRY(riros::launch_coverage(d_detect, d_events, d_words, F, T, cov_dst, s), "coverage");
     if (!on_dev) {
         HIP_TRY(hipMemcpyAsync(detect, d_detect, (size_t)F * 4, hipMemcpyDeviceToHost, s), "detect download");
         if (events)
             HIP_TRY(hipMemcpyAsync(events, d_events, (size_t)F * 8, hipMemcpyDeviceToHost, s), "events download");
+        if (opts->words)
+            HIP_TRY(hipMemcpyAsync(opts->words, d_words, (size_t)F * 8, hipMemcpyDeviceToHost, s),
+                    "words download");
         if (cov) HIP_TRY(hipMemcpyAsync(cov, d->d_cov, sizeof(riros_coverage), hipMemcpyDeviceToHost, s),
                          "coverage download");
         HIP_TRY(hipStreamSynchronize(s), "fault simulation sync");
@@ -706,6 +725,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     float* d_pr = nullptr;
     uint32_t* d_det = nullptr;
     uint64_t* d_ev = nullptr;
+    uint64_t* d_wk = nullptr;
     riros_coverage* d_cov = nullptr;
     riros::Slot* d_slots = nullptr;
     uint64_t* d_regs = nullptr;
@@ -723,6 +743,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (any_prio) A(batch_alloc(b, &d_pr, b->F));
     A(batch_alloc(b, &d_det, b->F));
     A(batch_alloc(b, &d_ev, b->F));
+    A(batch_alloc(b, &d_wk, b->F));
     A(batch_alloc(b, &d_cov, n));
     A(batch_alloc(b, &d_slots, (size_t)blocks * Nmax));
     A(batch_alloc(b, &d_regs, (size_t)blocks * 2 * std::max(Rmax, 1u)));
@@ -758,6 +779,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.ws = riros::PlainWorkspace{d_slots, d_regs, d_stamp};
     p.detect = d_det;
     p.events = d_ev;
+    p.words = d_wk;
     p.cov = d_cov;
     std::string err;
     int rc = riros::order_batch(b->tw, d_pr, b->F, opts->theta, &p.order, b->cap_stream, err);
@@ -799,7 +821,8 @@ int riros_batch_launch(riros_batch b, void* stream)
     return RIROS_OK;
 }
 
-int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, riros_coverage* cov)
+int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* events, uint64_t* words,
+                     riros_coverage* cov)
 {
     if (!b) return set_err(RIROS_EINVAL, "NULL campaign");
     if (i >= b->n) return set_err(RIROS_EINVAL, "design index out of range");
@@ -811,6 +834,8 @@ int riros_batch_read(riros_batch b, uint32_t i, uint32_t* detect, uint64_t* even
         HIP_TRY(hipMemcpy(detect, b->plan.detect + o, (size_t)cnt * 4, hipMemcpyDeviceToHost), "detect download");
         if (events)
             HIP_TRY(hipMemcpy(events, b->plan.events + o, (size_t)cnt * 8, hipMemcpyDeviceToHost), "events download");
+        if (words)
+            HIP_TRY(hipMemcpy(words, b->plan.words + o, (size_t)cnt * 8, hipMemcpyDeviceToHost), "words download");
     }
     if (cov) HIP_TRY(hipMemcpy(cov, b->plan.cov + i, sizeof(riros_coverage), hipMemcpyDeviceToHost), "coverage download");
     return RIROS_OK;

@@ -145,6 +145,14 @@ struct DesignSrc {
     const uint16_t* did;
 };
 
+// The site's golden word (one or two words) once per simulated cycle: the
+// fault-cycle term of the byte model.
+__device__ __forceinline__ uint64_t site_words(int drop, uint32_t det, uint32_t T, uint32_t width)
+{
+    const uint64_t cycles = (drop && det != RIROS_UNDETECTED) ? (uint64_t)det + 1u : (uint64_t)T;
+    return cycles * (width > 32 ? 2u : 1u);
+}
+
 // Phase 2: light faults one per lane.  A lane with no divergent register
 // skips straight to the next cycle in which its site is excited (the site's
 // bit differs from the stuck value), reading 64 cycles of that bit with one
@@ -156,7 +164,8 @@ template <int C, bool BATCH>
 __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict__ faults,
                             uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
-                            uint64_t* __restrict__ events_out, uint32_t lanes, uint32_t rate_num)
+                            uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out,
+                            uint32_t lanes, uint32_t rate_num)
 {
     // Register next-state deltas: a pipeline keeps one per divergent stage.
     // Batched lanes hold their design's pointers in registers, so they keep
@@ -169,7 +178,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
 
     uint32_t fi = kNone, site = 0, fbit = 0, fval = 0, ft0 = 0, t = 0, det = RIROS_UNDETECTED;
     uint32_t rk = 0;   // next entry of rcur to evaluate in this cycle
-    uint64_t ev = 0;
+    uint64_t ev = 0, wk = 0;   // events and byte-model words of the lane's fault
     bool in_cycle = false;
     uint64_t exw = 0;
     uint32_t ewb = kNone;
@@ -232,6 +241,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     t = 0;
                     det = RIROS_UNDETECTED;
                     ev = 0;
+                    wk = 0;
                     pend.n = div.n = rcur.n = rnxt.n = 0;
                     rk = 0;
                     in_cycle = false;
@@ -290,11 +300,13 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 if (!found) {
                     detect_out[fi] = det;
                     if (events_out) events_out[fi] = ev;
+                    words_out[fi] = wk + site_words(drop, det, d.T, srec.width);
                     fi = kNone;
                     finished = true;
                     continue;
                 }
                 ev++;
+                wk += srec.words;
                 on_divergent(site, 1ull << fbit, srec, sf0, sf1, sf2, sf3);
                 evaluated = true;
             } else {
@@ -347,7 +359,10 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             }
             if (n == site) delta = apply_fault(gv ^ delta, fbit, fval, t, ft0) ^ gv;
             const bool dout = delta != 0;
-            if (din || dout) ev++;
+            if (din || dout) {
+                ev++;
+                wk += (r.op == RIROS_OP_REG && din) ? 2u * r.words : r.words;
+            }
             if (dout) on_divergent(n, delta, r, p0, p1, p2, p3);
         }
 
@@ -379,6 +394,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             if (done) {
                 detect_out[fi] = det;
                 if (events_out) events_out[fi] = ev;
+                words_out[fi] = wk + site_words(drop, det, d.T, srec.width);
                 fi = kNone;
                 finished = true;
             }
@@ -391,21 +407,23 @@ template <bool BATCH>
 __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, const riros_fault* __restrict__ faults,
                                           int drop, const WaveLds& s, Slot* slots, uint64_t* regs,
                                           uint64_t& stamp0, uint32_t* __restrict__ detect_out,
-                                          uint64_t* __restrict__ events_out)
+                                          uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     uint32_t det;
-    uint64_t ev;
+    uint64_t ev, wk;
     if (BATCH) {
         const uint32_t k = src.did[fi];
         const DevDesign dd = src.td[k];
         const GoldenView gg = src.tg[k];
-        wave_sim_fault(dd, gg.G, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(dd, gg.G, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev, wk);
     } else {
-        wave_sim_fault(src.d, src.g.G, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev);
+        wave_sim_fault(src.d, src.g.G, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0,
+                       det, ev, wk);
     }
-    if (threadIdx.x == 0) {
+    if ((threadIdx.x & 63) == 0) {
         detect_out[fi] = det;
         if (events_out) events_out[fi] = ev;
+        words_out[fi] = wk;
     }
 }
 
@@ -431,7 +449,7 @@ template <bool BATCH>
 __device__ void drain_handover(const DesignSrc& src, const riros_fault* __restrict__ faults, uint32_t F,
                                uint32_t nlight, TwoDCounters* ctr, uint32_t* esc, int drop, const WaveLds& s, Slot* slots,
                                uint64_t* regs, uint64_t& stamp0, uint32_t* __restrict__ detect_out,
-                               uint64_t* __restrict__ events_out)
+                               uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     const uint32_t lane = threadIdx.x & 63;
     uint32_t idle = 0;
@@ -479,7 +497,7 @@ __device__ void drain_handover(const DesignSrc& src, const riros_fault* __restri
         fi = __shfl(fi, 0, 64);
         ticket = __shfl(ticket, 0, 64);
         if (__shfl((int)leave, 0, 64)) break;
-        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out);
+        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out, words_out);
         if (lane == 0) __hip_atomic_store(&esc[ticket], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         idle = 0;
     }
@@ -508,7 +526,8 @@ __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu
 void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
     const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-    uint32_t rate_num, int unified, uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out)
+    uint32_t rate_num, int unified, uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out,
+    uint64_t* __restrict__ words_out)
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
@@ -528,7 +547,7 @@ void k_twod_a(
                 idx = __shfl(idx, 0, 64);
                 if (idx >= nh) break;
                 heavy_one<BATCH>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
-                                 events_out);
+                                 events_out, words_out);
             }
         }
         // Phase 2: light faults, one per lane; each wavefront takes at most
@@ -537,13 +556,14 @@ void k_twod_a(
         const uint32_t waves = gridDim.x * (blockDim.x >> 6);
         const uint32_t lanes = min(64u, max(1u, (nlight + waves - 1) / waves));
         light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
-                              events_out, lanes, rate_num);
+                              events_out, words_out, lanes, rate_num);
         if (unified && wave == 0)
             drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
-                                  events_out);
+                                  events_out, words_out);
     } else {
         const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
-        light_phase<C, BATCH>(src, faults, F, order, ctr, esc, drop, detect_out, events_out, lanes, rate_num);
+        light_phase<C, BATCH>(src, faults, F, order, ctr, esc, drop, detect_out, events_out, words_out, lanes,
+                              rate_num);
     }
 }
 
@@ -553,7 +573,7 @@ template <bool BATCH>
 __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
                                                TwoDCounters* ctr, const uint32_t* __restrict__ esc, int drop,
                                                PlainWorkspace ws, uint64_t span, uint32_t* __restrict__ detect_out,
-                                               uint64_t* __restrict__ events_out)
+                                               uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     extern __shared__ uint32_t lds[];
     const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, mx.wpp);
@@ -570,7 +590,7 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
         if (idx >= n) break;
         const uint32_t fi = esc[idx];
         if (fi == kDone) continue;   // simulated in launch A (phase 3)
-        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out);
+        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out, words_out);
     }
 }
 
@@ -622,28 +642,32 @@ __global__ void k_reset_run_counters(TwoDCounters* ctr)
 // off[k]..off[k+1] with that design's cycle count.
 __global__ __launch_bounds__(256) void k_batch_coverage(const uint32_t* __restrict__ detect,
                                                         const uint64_t* __restrict__ events,
+                                                        const uint64_t* __restrict__ words,
                                                         const uint32_t* __restrict__ off,
                                                         const GoldenView* __restrict__ tg,
                                                         riros_coverage* __restrict__ cov)
 {
-    __shared__ unsigned long long red[3][4];
+    __shared__ unsigned long long red[4][4];
     const uint32_t k = blockIdx.x;
     const uint32_t T = tg[k].T;
-    unsigned long long det = 0, fc = 0, ev = 0;
+    unsigned long long det = 0, fc = 0, ev = 0, wk = 0;
     for (uint32_t i = off[k] + threadIdx.x; i < off[k + 1]; i += blockDim.x) {
         const uint32_t dc = detect[i];
         det += dc != RIROS_UNDETECTED;
         fc += dc != RIROS_UNDETECTED ? (unsigned long long)dc + 1 : T;
         ev += events[i];
+        wk += words[i];
     }
     det = wave_sum_u64(det);
     fc = wave_sum_u64(fc);
     ev = wave_sum_u64(ev);
+    wk = wave_sum_u64(wk);
     const uint32_t w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][w] = det;
         red[1][w] = fc;
         red[2][w] = ev;
+        red[3][w] = wk;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -651,6 +675,7 @@ __global__ __launch_bounds__(256) void k_batch_coverage(const uint32_t* __restri
         cov[k].total = off[k + 1] - off[k];
         cov[k].fault_cycles = red[1][0] + red[1][1] + red[1][2] + red[1][3];
         cov[k].events = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+        cov[k].words = red[3][0] + red[3][1] + red[3][2] + red[3][3];
     }
 }
 
@@ -750,7 +775,8 @@ template <int C, bool BATCH>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
                                 const uint32_t* order, bool heavy, int unified, int share, TwoDCounters* ctr,
                                 uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
-                                uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
+                                uint32_t rate_num, uint32_t* detect, uint64_t* events, uint64_t* words,
+                                hipStream_t s)
 {
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
     hipError_t e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -762,14 +788,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
-                           order, ctr, esc, drop, ws, rate_num, unified, detect, events);
+                           order, ctr, esc, drop, ws, rate_num, unified, detect, events, words);
     } else {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
-                           ctr, esc, drop, ws, rate_num, 0, detect, events);
+                           ctr, esc, drop, ws, rate_num, 0, detect, events, words);
     }
     const uint32_t bb = resident_blocks((const void*)k_twod_b<BATCH>, ldsb, blocks);
     hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(bb), dim3(64), ldsb, s, src, mx, faults, ctr, esc, drop, ws, span,
-                       detect, events);
+                       detect, events, words);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_advance_stamp(ws.stamp_dev, 2 * span, s);
@@ -779,12 +805,13 @@ template <bool BATCH>
 static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
                                   uint32_t F, const uint32_t* order, bool heavy, int unified, int share,
                                   TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
-                                  uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events, hipStream_t s)
+                                  uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
+                                  uint64_t* words, hipStream_t s)
 {
     switch (cap) {
-    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
-    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, s);
+    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
     }
 }
 
@@ -831,8 +858,8 @@ static int ensure_twod_ws(TwoDWorkspace& ws, uint32_t F, bool with_sort, TwoDLay
 
 int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const riros_fault* faults,
              const float* priority, uint32_t F, int drop, const TwoDParams& p, PlainWorkspace heavy_ws,
-             uint32_t blocks, uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
-             std::string& err)
+             uint32_t blocks, uint32_t* detect, uint64_t* events, uint64_t* words, hipEvent_t ev0, hipEvent_t ev1,
+             hipStream_t s, std::string& err)
 {
     TwoDLayout lay;
     int rc = ensure_twod_ws(ws, F, priority != nullptr, lay, err, s);
@@ -854,7 +881,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
     hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share, ctr, esc,
-                                          drop, heavy_ws, span, blocks, rate_num, detect, events, s);
+                                          drop, heavy_ws, span, blocks, rate_num, detect, events, words, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     return RIROS_OK;
@@ -911,7 +938,7 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
 #define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,     \
                        b.faults, b.F, b.order,                                                                   \
-                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events)
+                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events, b.words)
     if (b.unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((b.F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, b.F + kTicketPad,
                            kNone);
@@ -930,12 +957,12 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     }
 #undef RIROS_LAUNCH_A
     hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks_b), dim3(64), ldsb, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
-                       b.span, b.detect, b.events);
+                       b.span, b.detect, b.events, b.words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_advance_stamp(b.ws.stamp_dev, 2 * b.span, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_coverage, dim3(b.n), dim3(256), 0, s, b.detect, b.events, b.off, b.tg, b.cov);
+    hipLaunchKernelGGL(k_batch_coverage, dim3(b.n), dim3(256), 0, s, b.detect, b.events, b.words, b.off, b.tg, b.cov);
     return hipGetLastError();
 }
 

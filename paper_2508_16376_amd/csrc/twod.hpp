@@ -36,7 +36,7 @@ struct TwoDParams {
 int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gv,
              const riros_fault* faults, const float* priority, uint32_t F, int drop,
              const TwoDParams& p, PlainWorkspace heavy_ws, uint32_t heavy_blocks,
-             uint32_t* detect, uint64_t* events, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
+             uint32_t* detect, uint64_t* events, uint64_t* words, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s,
              std::string& err);
 
 // Synchronises s and checks the last run's counters: every handed-over fault
@@ -72,6 +72,7 @@ struct BatchPlan {
     PlainWorkspace ws{};
     uint32_t* detect = nullptr;
     uint64_t* events = nullptr;
+    uint64_t* words = nullptr;
     riros_coverage* cov = nullptr;
 };
 

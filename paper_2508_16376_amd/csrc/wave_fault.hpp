@@ -85,8 +85,10 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
 
 // Simulate fault f from cycle 0 (drop: stop after the detect cycle).  slots
 // is this wave's [N] faulty-value array, regs its [2][R] register next-state
-// ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform) and the
-// event count (wave total).  Must be called by all 64 lanes of one
+// ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform), the
+// event count and the byte-model words (wave totals; the words count each
+// event's NodeRec::words, a register event with divergent state twice, and
+// the site's golden word once per simulated cycle).  Must be called by all 64 lanes of one
 // wavefront; other wavefronts of its workgroup may run other work (it orders
 // its LDS accesses with wave_lds_sync, never a workgroup barrier).
 __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gr,
@@ -94,7 +96,8 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                                       const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
                                       const riros_fault f, int drop, const WaveLds& s,
                                       Slot* __restrict__ slots, uint64_t* __restrict__ regs,
-                                      uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out)
+                                      uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out,
+                                      uint64_t& words_out)
 {
     // The LDS arrays as local values rather than fields read through a
     // reference: code that chooses between two of them then selects
@@ -127,7 +130,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         rnsum[j] = 0;
     }
     for (uint32_t i = lane; i <= d.L; i += 64) lvloff[i] = d.lvl_off[i];
-    uint32_t ev = 0;
+    uint32_t ev = 0, wk = 0;
     uint32_t det = RIROS_UNDETECTED;
     wave_lds_sync();
     for (uint32_t t = 0; t < T; ++t) {
@@ -298,6 +301,8 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     if (n == site) v = apply_fault(v, fbit, fval, t, ft0);
                     const bool dout = v != gv;
                     ev += (din || dout) ? 1u : 0u;
+                    const uint32_t ew = (din || dout) ? (uint32_t)x.words : 0u;
+                    wk += (x.op == RIROS_OP_REG && din) ? 2u * ew : ew;
                     if (dout) {
                         Slot sl;
                         sl.v = v;
@@ -330,6 +335,8 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     stamp0 += T;
     det_out = det;
     ev_out = wave_sum_u64((uint64_t)ev);
+    const uint64_t cycles = (drop && det != RIROS_UNDETECTED) ? (uint64_t)det + 1u : (uint64_t)T;
+    words_out = wave_sum_u64((uint64_t)wk) + cycles * (d.uwidth[f.site] > 32 ? 2u : 1u);
 }
 
 }  // namespace riros

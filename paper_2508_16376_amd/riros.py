@@ -30,7 +30,8 @@ MODE_CONCURRENT = 2
 EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros_free_golden",
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
             "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad",
-            "riros_batch_create", "riros_batch_launch", "riros_batch_read", "riros_batch_free"]
+            "riros_batch_create", "riros_batch_launch", "riros_batch_read", "riros_batch_free",
+            "riros_peak_hbm", "riros_peak_valu"]
 N_FEATURES = 6
 MLP_PARAMS = 4673
 MLP_WEIGHTS = MLP_PARAMS + 12
@@ -52,7 +53,7 @@ class SimOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("priority", ctypes.c_void_p), ("theta", ctypes.c_float),
                 ("light_cap", ctypes.c_int32), ("unified", ctypes.c_int32), ("monitor_rate", ctypes.c_float),
                 ("struct_share", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("words", ctypes.c_void_p)]
 
 
 class TrainCfg(ctypes.Structure):
@@ -62,7 +63,7 @@ class TrainCfg(ctypes.Structure):
 
 class Coverage(ctypes.Structure):
     _fields_ = [("detected", ctypes.c_uint64), ("total", ctypes.c_uint64),
-                ("fault_cycles", ctypes.c_uint64), ("events", ctypes.c_uint64)]
+                ("fault_cycles", ctypes.c_uint64), ("events", ctypes.c_uint64), ("words", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -130,10 +131,14 @@ def lib():
         L.riros_batch_create.restype = I
         L.riros_batch_launch.argtypes = [P, P]
         L.riros_batch_launch.restype = I
-        L.riros_batch_read.argtypes = [P, U, P, P, ctypes.POINTER(Coverage)]
+        L.riros_batch_read.argtypes = [P, U, P, P, P, ctypes.POINTER(Coverage)]
         L.riros_batch_read.restype = I
         L.riros_batch_free.argtypes = [P]
         L.riros_batch_free.restype = None
+        L.riros_peak_hbm.argtypes = [ctypes.c_uint64, I, ctypes.POINTER(ctypes.c_double), P]
+        L.riros_peak_hbm.restype = I
+        L.riros_peak_valu.argtypes = [I, ctypes.POINTER(ctypes.c_double), P]
+        L.riros_peak_valu.restype = I
         _lib = L
     return _lib
 
@@ -220,23 +225,31 @@ class Golden:
             pass
 
 
+# Words of device memory per riros_coverage (detected, total, fault_cycles, events, words).
+COVERAGE_FIELDS = 5
+
+
 def make_opts(mode=MODE_PLAIN, drop=True, io_on_device=False, waves_per_cu=0, priority=None,
-              theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None, struct_share=0) -> SimOpts:
+              theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None, struct_share=0,
+              words=None) -> SimOpts:
     return SimOpts(mode, 1 if drop else 0, 1 if io_on_device else 0, waves_per_cu, _ptr(priority),
-                   theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream))
+                   theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream), _ptr(words))
 
 
 def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_PLAIN, drop=True,
               waves_per_cu=0, priority=None, theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0,
-              stream=None, with_events=True, struct_share=0):
-    """riros_fault_sim on host arrays: returns (detect, events, coverage dict)."""
+              stream=None, with_events=True, struct_share=0, words_out=None):
+    """riros_fault_sim on host arrays: returns (detect, events, coverage dict).
+    words_out (optional uint64[F]) receives the per-fault byte-model words."""
     fl = np.ascontiguousarray(faults)
     F = fl.size
     detect = np.empty(F, dtype=np.uint32)
     events = np.empty(F, dtype=np.uint64) if with_events else None
     pr = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
+    if words_out is not None:
+        assert words_out.dtype == np.uint64 and words_out.size == F and words_out.flags.c_contiguous
     opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, unified, monitor_rate, stream,
-                     struct_share)
+                     struct_share, words_out)
     cov = Coverage()
     _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(fl), F, ctypes.byref(opts), _ptr(detect),
                                  _ptr(events), ctypes.byref(cov)))
@@ -340,11 +353,15 @@ class Batch:
     def launch(self, stream=None):
         _check(lib().riros_batch_launch(self.handle, _stream_ptr(stream)))
 
-    def read(self, i):
+    def read(self, i, words_out=None):
+        """(detect, events, coverage dict) of design i; words_out (optional
+        uint64[F[i]]) receives its per-fault byte-model words."""
         det = np.empty(self.F[i], dtype=np.uint32)
         ev = np.empty(self.F[i], dtype=np.uint64)
+        if words_out is not None:
+            assert words_out.dtype == np.uint64 and words_out.size == self.F[i]
         cov = Coverage()
-        _check(lib().riros_batch_read(self.handle, i, _ptr(det), _ptr(ev), ctypes.byref(cov)))
+        _check(lib().riros_batch_read(self.handle, i, _ptr(det), _ptr(ev), _ptr(words_out), ctypes.byref(cov)))
         return det, ev, cov.as_dict()
 
     def close(self):
@@ -357,3 +374,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def peak_hbm_gbs(nbytes: int = 2 << 30, reps: int = 5, stream=None) -> float:
+    """riros_peak_hbm: best streaming-copy rate in GB/s (bytes read + written)."""
+    out = ctypes.c_double()
+    rc = lib().riros_peak_hbm(nbytes, reps, ctypes.byref(out), _stream_ptr(stream))
+    if rc:
+        raise RirosError(rc, "HBM probe failed")
+    return float(out.value)
+
+
+def peak_valu_ops(reps: int = 5, stream=None) -> float:
+    """riros_peak_valu: best int32 vector-ALU rate, instructions per second per lane."""
+    out = ctypes.c_double()
+    rc = lib().riros_peak_valu(reps, ctypes.byref(out), _stream_ptr(stream))
+    if rc:
+        raise RirosError(rc, "VALU probe failed")
+    return float(out.value)

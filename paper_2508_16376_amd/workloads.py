@@ -416,20 +416,26 @@ def gen_templates(seed: int, *, n_nodes: int, n_pi: int = 128, acc_share: float 
                   name: str = "templates") -> Design:
     """Design assembled from seeded templates sharing the primary inputs:
 
-      pipelined datapath  k = 3..8 register stages of width 8/16/32, each stage
-                          mixing the previous stage with a primary-input slice
-                          (ADD/XOR/SUB, some MUX and AND masking); the last
-                          stage is an output, so a divergence reaches it within
-                          k cycles or dies out;
-      FSM                 8-bit state, next state chosen by a compare on an
-                          input slice between two update rules; the state,
-                          mixed with an input, is an output;
+      pipelined datapath  k = 2..4 register stages of width 8/16/32; the first
+                          stage takes the XOR of two input slices (masked by
+                          a constant AND in some pipelines, before any
+                          register, so a masked bit never reaches state); each
+                          stage mixes its register with an input slice
+                          (ADD/XOR/SUB), some stages choosing by an input
+                          compare between two such updates; the last stage is
+                          an output, so a divergence reaches it within k
+                          cycles of its excitation;
+      FSM                 8-bit state, next state chosen by an input bit
+                          between two update rules; the state, mixed with an
+                          input, is an output;
       accumulator         32-bit acc <- acc + (a ^ b) observed only through
                           acc == constant; a divergence stays in the state for
                           the whole run without reaching an output.
 
     Accumulators are added until they hold about ``acc_share`` of the bits
-    that can carry a fault.
+    that can carry a fault, so about that share of a uniform fault list stays
+    latent in state, and nearly all other faults are detected, or leave no
+    divergent state, within ten cycles.
     """
     st = Stream(sub_seed(seed, 1))
     net = _Net()
@@ -440,16 +446,16 @@ def gen_templates(seed: int, *, n_nodes: int, n_pi: int = 128, acc_share: float 
     acc_bits = 0
     all_bits = 0
 
-    def pi_slice(w):
-        p = pis[st.below(n_pi)]
-        if w == 32:
-            return p
-        return net.add(SLICE, w, (p,), st.below(33 - w))
-
     def count(n):
         nonlocal all_bits
         all_bits += net.w[n]
         return n
+
+    def pi_slice(w):
+        p = pis[st.below(n_pi)]
+        if w == 32:
+            return p
+        return count(net.add(SLICE, w, (p,), st.below(33 - w)))
 
     while len(net.op) < n_nodes:
         want_acc = acc_bits < acc_share * max(all_bits, 1)
@@ -457,24 +463,24 @@ def gen_templates(seed: int, *, n_nodes: int, n_pi: int = 128, acc_share: float 
         if kind == 0:
             # pipelined datapath
             w = (8, 16, 32)[st.below(3)]
-            k = 3 + st.below(6)
+            k = 2 + st.below(3)
             v = count(net.add(XOR, w, (pi_slice(w), pi_slice(w))))
+            if st.uniform() < 0.15:
+                m = net.add(CONST, w, (), int(st.u64() & mask_of(w)))
+                v = count(net.add(AND, w, (v, m)))
             for _ in range(k):
                 r = count(net.add(REG, w, (v,), 0))
                 op = (ADD, XOR, SUB, ADD, XOR)[st.below(5)]
                 v = count(net.add(op, w, (r, pi_slice(w))))
-                u = st.uniform()
-                if u < 0.15:
-                    m = net.add(CONST, w, (), int(st.u64() & mask_of(w)))
-                    v = count(net.add(AND, w, (v, m)))
-                elif u < 0.3:
-                    sel = count(net.add(ULT, 1, (pi_slice(8), net.add(CONST, 8, (), 200))))
-                    v = count(net.add(MUX, w, (sel, v, r)))
+                if st.uniform() < 0.08:
+                    sel = count(net.add(ULT, 1, (pi_slice(8), net.add(CONST, 8, (), 128))))
+                    alt = count(net.add(XOR, w, (r, pi_slice(w))))
+                    v = count(net.add(MUX, w, (sel, v, alt)))
             po.append(v)
         elif kind == 1:
             # FSM with 8-bit state
             s = count(net.add(REG, 8, (0,), 0))
-            cond = count(net.add(EQ, 1, (pi_slice(2), net.add(CONST, 2, (), st.below(4)))))
+            cond = count(net.add(EQ, 1, (pi_slice(1), net.add(CONST, 1, (), st.below(2)))))
             a = count(net.add(ADD, 8, (s, net.add(CONST, 8, (), 1 + st.below(255)))))
             b = count(net.add(XOR, 8, (s, pi_slice(8))))
             nxt = count(net.add(MUX, 8, (cond, a, b)))
@@ -488,7 +494,7 @@ def gen_templates(seed: int, *, n_nodes: int, n_pi: int = 128, acc_share: float 
             net.set_in0(acc, s2)
             k = net.add(CONST, 32, (), int(st.u64() & 0xFFFFFFFF))
             po.append(count(net.add(EQ, 1, (acc, k))))
-            acc_bits += 96
+            acc_bits += 97
     meta = {"acc_share": acc_share, "acc_bits": acc_bits, "fault_bits": all_bits}
     return net.design(po, n_pi, name, meta)
 
@@ -636,11 +642,13 @@ def large(seed: int | None = None, F: int = 1000000, T: int = 10000, n_nodes: in
 
 
 def campaign(seed: int | None = None, n: int = 64, nodes=(1000, 50000), faults=(1000, 100000),
-             cycles=(500, 5000)) -> list[Workload]:
+             cycles=(500, 5000), only=None) -> list[Workload]:
     """Batched campaign: n independent layered designs with node counts
     log-uniform in ``nodes``, register fraction uniform in 3..10 %, fault
     counts log-uniform in ``faults`` and cycle counts uniform in ``cycles``.
-    Design k is seeded with the campaign seed + 1000 (k + 1)."""
+    Design k is seeded with the campaign seed + 1000 (k + 1).  ``only``: build
+    just these design indexes (the others' sizes are still drawn, so design k
+    is the same either way)."""
     s = config_seed(3) if seed is None else seed
     st = Stream(sub_seed(s, 7))
     out = []
@@ -650,6 +658,8 @@ def campaign(seed: int | None = None, n: int = 64, nodes=(1000, 50000), faults=(
         rf = 0.03 + 0.07 * st.uniform()
         F = int(round(math.exp(math.log(faults[0]) + st.uniform() * (math.log(faults[1]) - math.log(faults[0])))))
         T = cycles[0] + st.below(cycles[1] - cycles[0] + 1)
+        if only is not None and k not in only:
+            continue
         n_pi = min(128, max(8, N // 300))
         d = gen_layered(sk, n_nodes=N, n_regs=max(1, int(rf * N)), n_pi=n_pi, n_po=max(1, n_pi // 2),
                         n_levels=min(40, max(4, N // 100)), widths=[1, 8, 16, 32, 64], wweights=[2, 3, 2, 2, 1],

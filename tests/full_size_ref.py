@@ -1,0 +1,69 @@
+"""The oracle's results on every fault of the full-size workloads, computed
+once per test process and shared by the test modules that compare with them.
+
+The oracle (O1: only nodes with a divergent input, its own code) runs on the
+host over all the host's cores: the heavy-tailed list (200,000 faults, 5,000
+cycles) and the large list (1,000,000 faults, 10,000 cycles) take well under
+a minute each, most of it the oracle's single-threaded golden trace; the
+64-design campaign computes its designs' goldens and fault lists in parallel
+threads.  Nothing here comes from the GPU library.
+"""
+from __future__ import annotations
+
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+import oracle
+from paper_2508_16376_amd import workloads as W
+
+_CACHE: dict = {}
+
+
+def _log(msg: str):
+    print(msg, flush=True)
+
+
+def _one(w, nthreads):
+    G = oracle.golden(w.design, w.stimulus, w.T)
+    det, ev, words, _ = oracle.fault_sim_stats(w.design, w.stimulus, w.T, w.faults, G=G, nthreads=nthreads)
+    del G
+    return det, ev, words
+
+
+def single(name: str):
+    """(workload, detect, events, words) of 'heavy_tailed' or 'large', drop on."""
+    if name not in _CACHE:
+        t = time.time()
+        w = {"heavy_tailed": W.heavy_tailed, "large": W.large}[name]()
+        det, ev, words = _one(w, oracle.default_threads())
+        _log(f"[oracle] {name}: {w.faults.size} faults in {time.time() - t:.1f}s")
+        _CACHE[name] = (w, det, ev, words)
+    return _CACHE[name]
+
+
+def campaign():
+    """[(workload, detect, events, words)] for the 64 designs of the campaign."""
+    if "campaign" not in _CACHE:
+        t = time.time()
+        ws = W.campaign()
+        cores = oracle.default_threads()
+        workers = max(1, min(8, cores // 2))
+        per = max(1, cores // workers)
+        # largest designs first, so the pool ends together
+        order = sorted(range(len(ws)), key=lambda i: -ws[i].design.num_nodes * ws[i].T)
+        res = [None] * len(ws)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            futs = {i: ex.submit(_one, ws[i], per) for i in order}
+            for i in order:
+                res[i] = futs[i].result()
+        _log(f"[oracle] campaign: {sum(w.faults.size for w in ws)} faults of {len(ws)} designs in "
+             f"{time.time() - t:.1f}s")
+        _CACHE["campaign"] = [(w,) + r for w, r in zip(ws, res)]
+    return _CACHE["campaign"]
+
+
+def fault_cycles(detect: np.ndarray, T: int) -> int:
+    return oracle.fault_cycles(detect, T)
+

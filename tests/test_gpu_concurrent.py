@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from golden import make_expected
+import full_size_ref as ref
 from paper_2508_16376_amd import riros
 from paper_2508_16376_amd import workloads as W
 
@@ -67,7 +67,7 @@ def test_device_io(many, many_oracle):
     f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
     det = torch.empty(F, dtype=torch.int32, device=dev)
     ev = torch.empty(F, dtype=torch.int64, device=dev)
-    cov = torch.zeros(4, dtype=torch.int64, device=dev)
+    cov = torch.zeros(riros.COVERAGE_FIELDS, dtype=torch.int64, device=dev)
     opts = riros.make_opts(CONC, True, True, stream=torch.cuda.current_stream())
     riros.fault_sim_device(d, g, f_dev, F, det, ev, cov, opts)
     torch.cuda.synchronize()
@@ -102,18 +102,21 @@ def test_one_site_many_faults():
         np.testing.assert_array_equal(ev, oev)
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("name", ["heavy_tailed", "large"])
-def test_full_size_against_stored_oracle_sample(name):
-    digest, idx, odet, oev = make_expected.read(name)
-    w = make_expected.MAKERS[name][0]()
-    assert make_expected.workload_digest(w) == digest, \
-        "the workload generator changed; rerun tests/golden/make_expected.py"
+def test_full_size_every_fault(name):
+    """Every fault of the full-size lists against the oracle, and the same
+    results as the two-dimensional schedule."""
+    w, odet, oev, owk = ref.single(name)
     print(f"[concurrent full-size] {name}: N={w.design.num_nodes} T={w.T} F={w.faults.size}", flush=True)
     d = riros.Design(w.design)
     g = riros.Golden(d, w.stimulus, w.T)
-    det, ev, cov = riros.fault_sim(d, g, w.faults, mode=CONC)
-    np.testing.assert_array_equal(det[idx], odet)
-    np.testing.assert_array_equal(ev[idx], oev)
+    wk = np.empty(w.faults.size, dtype=np.uint64)
+    det, ev, cov = riros.fault_sim(d, g, w.faults, mode=CONC, words_out=wk)
+    np.testing.assert_array_equal(det, odet)
+    np.testing.assert_array_equal(ev, oev)
+    np.testing.assert_array_equal(wk, owk)
+    assert cov["words"] == int(owk.sum()) and cov["events"] == int(oev.sum())
     print(f"[concurrent full-size] {name}: two-dimensional", flush=True)
     tdet, tev, tcov = riros.fault_sim(d, g, w.faults, mode=riros.MODE_TWO_D, monitor_rate=2.0, unified=1)
     np.testing.assert_array_equal(det, tdet)

@@ -1,18 +1,19 @@
-"""Full-size parity for the heavy-tailed and large workloads.
+"""Full-size parity: every fault of the heavy-tailed (200,000 faults, 5,000
+cycles), large (1,000,000 faults, 10,000 cycles) and batched-campaign (64
+designs) workloads against the oracle, bit-exact: detect cycle, event count
+and byte-model words of each fault, and the coverage totals.
 
-The oracle cannot finish these fault lists inside a test, so its results on a
-seeded sample of each list were stored by tests/golden/make_expected.py (which
-calls only the oracle).  Here the whole list runs on the GPU, in the launch
-configuration the benchmark times (two-dimensional mode, device-resident
-inputs and outputs, predicted priorities with a heavy threshold, the
-monitor on) and in plain mode; the sampled faults must match the oracle
-exactly and the two modes must agree on every fault.
+The oracle runs on the host in the same process (tests/full_size_ref.py).
+The GPU runs use the benchmark's kind of launch: two-dimensional mode with
+device-resident inputs and outputs, predicted priorities with a heavy
+threshold, the monitor and the unified schedule; plain mode runs the same
+lists.
 """
 import numpy as np
 import pytest
 import torch
 
-from golden import make_expected
+import full_size_ref as ref
 from paper_2508_16376_amd import riros
 from paper_2508_16376_amd import workloads as W
 
@@ -26,42 +27,71 @@ def _device_run(d, g, w, opts):
     f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
     det = torch.empty(F, dtype=torch.int32, device=dev)
     ev = torch.empty(F, dtype=torch.int64, device=dev)
-    cov = torch.zeros(4, dtype=torch.int64, device=dev)
+    wk = torch.empty(F, dtype=torch.int64, device=dev)
+    cov = torch.zeros(riros.COVERAGE_FIELDS, dtype=torch.int64, device=dev)
+    opts.words = wk.data_ptr()
     riros.fault_sim_device(d, g, f_dev, F, det, ev, cov, opts)
     torch.cuda.synchronize()
     return (det.cpu().numpy().view(np.uint32).copy(), ev.cpu().numpy().view(np.uint64).copy(),
-            cov.cpu().numpy().astype(np.int64))
+            wk.cpu().numpy().view(np.uint64).copy(), cov.cpu().numpy().astype(np.int64))
 
 
+def _compare(name, w, det, ev, wk, cov, odet, oev, owk):
+    bad = np.flatnonzero((det != odet) | (ev != oev) | (wk != owk))
+    assert bad.size == 0, (f"{name}: {bad.size} faults differ from the oracle, first {bad[:5].tolist()}: "
+                           f"gpu {det[bad[:5]].tolist()} {ev[bad[:5]].tolist()} oracle {odet[bad[:5]].tolist()} "
+                           f"{oev[bad[:5]].tolist()}")
+    assert cov[0] == int((odet != UND).sum()) and cov[1] == w.faults.size
+    assert cov[2] == ref.fault_cycles(odet, w.T)
+    assert cov[3] == int(oev.sum()) and cov[4] == int(owk.sum())
+
+
+def _priorities(d, g, w, seed=11):
+    """Priorities as the benchmark computes them: features, then network
+    inference (seeded initial weights here; any priority gives the same
+    results)."""
+    feats = riros.features(d, g, w.faults)
+    wts = np.concatenate([W.mlp_init_weights(seed), np.zeros(6, np.float32), np.ones(6, np.float32)])
+    return riros.mlp_predict(wts, feats)
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("name", ["heavy_tailed", "large"])
-def test_full_size_against_stored_oracle_sample(name):
-    digest, idx, odet, oev = make_expected.read(name)
-    w = make_expected.MAKERS[name][0]()
-    print(f"[full-size] {name}: N={w.design.num_nodes} T={w.T} F={w.faults.size} sample={idx.size}", flush=True)
-    assert make_expected.workload_digest(w) == digest, \
-        "the workload generator changed; rerun tests/golden/make_expected.py"
+def test_full_size_every_fault(name):
+    w, odet, oev, owk = ref.single(name)
+    print(f"[full-size] {name}: N={w.design.num_nodes} T={w.T} F={w.faults.size}", flush=True)
     d = riros.Design(w.design)
     g = riros.Golden(d, w.stimulus, w.T)
-
-    # Priorities as the benchmark computes them: features, then MLP inference
-    # (seeded initial weights here; any priority must give the same results).
-    feats = riros.features(d, g, w.faults)
-    wts = np.concatenate([W.mlp_init_weights(11), np.zeros(6, np.float32), np.ones(6, np.float32)])
-    pred = riros.mlp_predict(wts, feats)
+    pred = _priorities(d, g, w)
     prio = torch.from_numpy(np.ascontiguousarray(pred, np.float32)).cuda()
-    theta = float(np.quantile(pred, 0.99))
     s = torch.cuda.current_stream()
-    opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio, theta=theta,
-                           monitor_rate=1.0, light_cap=8, waves_per_cu=12, unified=1)
-    det, ev, cov = _device_run(d, g, w, opts)
-    np.testing.assert_array_equal(det[idx], odet)
-    np.testing.assert_array_equal(ev[idx], oev)
-    fc = int(np.where(det == UND, w.T, det.astype(np.int64) + 1).sum())
-    assert cov[0] == int((det != UND).sum()) and cov[1] == w.faults.size
-    assert cov[2] == fc and cov[3] == int(ev.sum())
-
+    opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio,
+                           theta=float(np.quantile(pred, 0.99)), monitor_rate=1.0, light_cap=8, waves_per_cu=12,
+                           unified=1)
+    _compare(name + " two-dimensional", w, *_device_run(d, g, w, opts), odet, oev, owk)
     print(f"[full-size] {name}: plain", flush=True)
-    pdet, pev, pcov = _device_run(d, g, w, riros.make_opts(riros.MODE_PLAIN, True, True, stream=s))
-    np.testing.assert_array_equal(pdet, det)
-    np.testing.assert_array_equal(pev, ev)
-    np.testing.assert_array_equal(pcov, cov)
+    _compare(name + " plain", w, *_device_run(d, g, w, riros.make_opts(riros.MODE_PLAIN, True, True, stream=s)),
+             odet, oev, owk)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_campaign_every_fault():
+    """The 64-design campaign in one graph launch (predicted priorities with a
+    heavy threshold, monitor, unified schedule), two replays; every fault of
+    every design against the oracle."""
+    refs = ref.campaign()
+    print(f"[full-size] campaign: {sum(r[0].faults.size for r in refs)} faults", flush=True)
+    ws = [r[0] for r in refs]
+    ds = [riros.Design(w.design) for w in ws]
+    gs = [riros.Golden(d, w.stimulus, w.T) for d, w in zip(ds, ws)]
+    prios = [_priorities(d, g, w) for d, g, w in zip(ds, gs, ws)]
+    theta = float(np.quantile(np.concatenate(prios), 0.95))
+    b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=theta, monitor_rate=2.0, unified=1)
+    for rep in range(2):
+        b.launch()
+        for i, (w, odet, oev, owk) in enumerate(refs):
+            wk = np.empty(w.faults.size, dtype=np.uint64)
+            det, ev, cov = b.read(i, words_out=wk)
+            c = np.array([cov["detected"], cov["total"], cov["fault_cycles"], cov["events"], cov["words"]])
+            _compare(f"campaign design {i} replay {rep}", w, det, ev, wk, c, odet, oev, owk)
+    b.close()

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path against the CPU oracle, bit-exact.
 
-Golden traces, detect cycles and event counts must be identical to the
-oracle's on the same seeded inputs.  Runs on an MI355X only.
+Golden traces, detect cycles, event counts and the byte-model words must be
+identical to the oracle's on the same seeded inputs.  Runs on an MI355X only.
 """
 import numpy as np
 import pytest
@@ -17,24 +17,27 @@ MODES = [pytest.param(riros.MODE_PLAIN, id="plain"), pytest.param(riros.MODE_TWO
          pytest.param(riros.MODE_CONCURRENT, id="concurrent")]
 
 
-def _run(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, **kw):
+def _run(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, words_out=None, **kw):
     d = riros.Design(design_np)
     g = riros.Golden(d, stim, T)
-    det, ev, cov = riros.fault_sim(d, g, fl, mode=mode, drop=drop, **kw)
+    det, ev, cov = riros.fault_sim(d, g, fl, mode=mode, drop=drop, words_out=words_out, **kw)
     return det, ev, cov, d, g
 
 
 def _check(design_np, stim, T, fl, mode=riros.MODE_PLAIN, drop=True, variant=1, **kw):
     print(f"[parity] design={design_np.name} N={design_np.num_nodes} T={T} F={fl.size} mode={mode} "
           f"drop={drop}", flush=True)
-    det, ev, cov, d, g = _run(design_np, stim, T, fl, mode, drop, **kw)
-    odet, oev = oracle.fault_sim(design_np, stim, T, fl, drop=drop, variant=variant)
+    words = np.empty(fl.size, dtype=np.uint64)
+    det, ev, cov, d, g = _run(design_np, stim, T, fl, mode, drop, words_out=words, **kw)
+    odet, oev, owords, _ = oracle.fault_sim_stats(design_np, stim, T, fl, drop=drop, variant=variant)
     np.testing.assert_array_equal(det, odet)
     np.testing.assert_array_equal(ev, oev)
+    np.testing.assert_array_equal(words, owords)
     assert cov["total"] == fl.size
     assert cov["detected"] == int((odet != UND).sum())
     assert cov["fault_cycles"] == oracle.fault_cycles(odet, T)
     assert cov["events"] == int(oev.sum())
+    assert cov["words"] == int(owords.sum())
     return det, ev
 
 
@@ -189,7 +192,7 @@ def test_device_io_matches_host_io(small):
     f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
     det_dev = torch.empty(w.faults.size, dtype=torch.int32, device=dev)
     ev_dev = torch.empty(w.faults.size, dtype=torch.int64, device=dev)
-    cov_dev = torch.zeros(4, dtype=torch.int64, device=dev)
+    cov_dev = torch.zeros(riros.COVERAGE_FIELDS, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     opts = riros.make_opts(riros.MODE_PLAIN, True, True, stream=stream)
     riros.fault_sim_device(d, g, f_dev, w.faults.size, det_dev, ev_dev, cov_dev, opts)
@@ -197,7 +200,7 @@ def test_device_io_matches_host_io(small):
     np.testing.assert_array_equal(det_dev.cpu().numpy().view(np.uint32), det)
     np.testing.assert_array_equal(ev_dev.cpu().numpy().view(np.uint64), ev)
     c = cov_dev.cpu().numpy()
-    assert list(c) == [cov["detected"], cov["total"], cov["fault_cycles"], cov["events"]]
+    assert list(c) == [cov["detected"], cov["total"], cov["fault_cycles"], cov["events"], cov["words"]]
 
 
 @pytest.mark.parametrize("light_cap", [4, 8, 16])
@@ -292,7 +295,7 @@ def test_two_d_device_io_with_priority(small):
     f_dev = torch.from_numpy(w.faults.view(np.uint8).copy()).to(dev)
     det_dev = torch.empty(w.faults.size, dtype=torch.int32, device=dev)
     ev_dev = torch.empty(w.faults.size, dtype=torch.int64, device=dev)
-    cov_dev = torch.zeros(4, dtype=torch.int64, device=dev)
+    cov_dev = torch.zeros(riros.COVERAGE_FIELDS, dtype=torch.int64, device=dev)
     opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=torch.cuda.current_stream(), priority=prio,
                            theta=90.0)
     riros.fault_sim_device(d, g, f_dev, w.faults.size, det_dev, ev_dev, cov_dev, opts)
