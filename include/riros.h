@@ -118,6 +118,14 @@ int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void*
                      riros_golden* out);
 void riros_free_golden(riros_golden g);
 
+/* riros_golden_sim for n designs at once: one kernel launch simulates every
+ * design's fault-free machine, one workgroup per design (the designs are
+ * independent), then each trace gets its other layouts.  stimulus[i] and T[i]
+ * as for riros_golden_sim; out[i] receives design i's handle.  Errors as for
+ * riros_golden_sim (nothing is returned on failure). */
+int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_t* const* stimulus,
+                          const uint32_t* T, void* stream, riros_golden* out);
+
 /* Copy cycles [t0, t0+nt) of a golden trace to host memory as
  * uint64[nt][num_nodes], in the caller's node numbering. */
 int riros_golden_read(riros_golden g, uint32_t t0, uint32_t nt, uint64_t* out);
@@ -178,6 +186,18 @@ typedef struct {
                               faulty value); a register whose state diverges, 2 words
                               more (state read and written); every word counts twice
                               for a node wider than 32 bits.  4 bytes a word. */
+    int32_t campaign_golden; /* riros_batch_create only: 1 = every launch of the
+                              campaign also recomputes each design's golden trace
+                              (one workgroup per design, one kernel) before its fault
+                              simulation, inside the same graph; 0 = the traces
+                              riros_golden_sim computed are used as they are */
+    int32_t heavy_wg;      /* TWO_D: threads that simulate one fault on the structural
+                              path in launch B (handed-over faults) and, when launch A
+                              runs workgroups of several wavefronts (struct_share), in
+                              its heavy prefix: 64 (one wavefront), 128 or 256 (the
+                              fault's frontier split across 2 or 4 wavefronts, one
+                              barrier per pass: the paper spreads a high-load node
+                              over many workers, Sec. IV-C); 0 = 64 */
 } riros_sim_opts;
 
 typedef struct {

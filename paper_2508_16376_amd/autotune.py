@@ -5,7 +5,8 @@ decide where work runs: whether idle wavefronts take handed-over faults
 during the light launch (the unified schedule), the events-per-cycle
 threshold of the light-lane monitor, the light-lane capacity, the number of
 resident wavefronts per compute unit, how many of them share one structural
-workspace, and (with a predictor) the
+workspace, how many wavefronts simulate one structural fault together, and
+(with a predictor) the
 predicted-load quantile above which faults start on the structural path.  The paper fixes its overload threshold
 by hand (Sec. V-A); here candidates are timed and the fastest kept, one
 parameter at a time (coordinate descent), with the result cached by design
@@ -37,10 +38,11 @@ SPACE = {
     "unified": [1, 0],
     "waves_per_cu": [8, 12, 16],
     "struct_share": [1, 2, 4],
+    "heavy_wg": [64, 128, 256],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
-           "heavy_quantile": None}
+           "heavy_wg": 64, "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -54,7 +56,8 @@ def _opts(p, priority):
     if priority is not None and p["heavy_quantile"] is not None:
         theta = float(np.quantile(priority, p["heavy_quantile"]))
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
-            "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0), "theta": theta}
+            "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0),
+            "heavy_wg": p.get("heavy_wg", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):

@@ -52,6 +52,18 @@ struct __attribute__((aligned(16))) Slot {
 
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s);
 
+// One design's golden run of a batched launch: its device stimulus [T][npi],
+// cycle count and row-major trace.
+struct GoldenJob {
+    const uint64_t* stim;
+    uint64_t* G;
+    uint32_t T;
+};
+
+// n designs' golden traces in one launch, one workgroup per design (td, jobs:
+// device tables of n entries).
+hipError_t launch_golden_many(uint32_t n, const DevDesign* td, const GoldenJob* jobs, hipStream_t s);
+
 struct PlainWorkspace {
     Slot* slots;              // [blocks][N]
     uint64_t* regs;           // [blocks][2][R]

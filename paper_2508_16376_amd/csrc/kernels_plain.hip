@@ -9,10 +9,11 @@ namespace riros {
 // ---------------------------------------------------------------------------
 // Golden machine: one workgroup walks the levels of every cycle; the nodes of a
 // level are independent and are spread over the workgroup's lanes.  Row t of G
-// is the working array of cycle t; registers read row t-1.
+// is the working array of cycle t; registers read row t-1.  A campaign runs
+// one workgroup per design in a single launch (its designs are independent).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_golden(DevDesign d, const uint64_t* __restrict__ stim,
-                                                 uint32_t T, uint64_t* __restrict__ G)
+__device__ void golden_design(const DevDesign& d, const uint64_t* __restrict__ stim, uint32_t T,
+                              uint64_t* __restrict__ G)
 {
     const uint32_t N = d.N;
     for (uint32_t t = 0; t < T; ++t) {
@@ -42,9 +43,30 @@ __global__ __launch_bounds__(1024) void k_golden(DevDesign d, const uint64_t* __
     }
 }
 
+__global__ __launch_bounds__(1024) void k_golden(DevDesign d, const uint64_t* __restrict__ stim, uint32_t T,
+                                                 uint64_t* __restrict__ G)
+{
+    golden_design(d, stim, T, G);
+}
+
+// Workgroup k: design k of a campaign (device tables of n entries).
+__global__ __launch_bounds__(1024) void k_golden_many(const DevDesign* __restrict__ td,
+                                                      const GoldenJob* __restrict__ jobs)
+{
+    const GoldenJob j = jobs[blockIdx.x];
+    golden_design(td[blockIdx.x], j.stim, j.T, j.G);
+}
+
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s)
 {
     hipLaunchKernelGGL(k_golden, dim3(1), dim3(1024), 0, s, d, stim, T, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_golden_many(uint32_t n, const DevDesign* td, const GoldenJob* jobs, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_golden_many, dim3(n), dim3(1024), 0, s, td, jobs);
     return hipGetLastError();
 }
 

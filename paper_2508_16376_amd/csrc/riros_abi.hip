@@ -34,6 +34,11 @@ bool valid_share(int32_t v)
     return v == 0 || v == 1 || v == 2 || v == 4;
 }
 
+bool valid_heavy_wg(int32_t v)
+{
+    return v == 0 || v == 64 || v == 128 || v == 256;
+}
+
 int hip_err(hipError_t e, const char* what)
 {
     char buf[256];
@@ -117,6 +122,7 @@ struct riros_golden_s {
     uint64_t* G = nullptr;    // row-major [T][N]
     uint64_t* Gn = nullptr;   // node-major [N][T]
     uint64_t* Bp = nullptr;   // bit-planes [bp_rows][ceil(T/64)]
+    uint64_t* stim = nullptr; // the stimulus [T][npi] (a campaign graph may recompute the trace)
     riros::GoldenView view() const { return riros::GoldenView{G, Gn, Bp, T, (T + 63) / 64}; }
 };
 
@@ -125,7 +131,25 @@ static void free_golden_mem(riros_golden g)
     if (g->G) (void)hipFree(g->G);
     if (g->Gn) (void)hipFree(g->Gn);
     if (g->Bp) (void)hipFree(g->Bp);
-    g->G = g->Gn = g->Bp = nullptr;
+    if (g->stim) (void)hipFree(g->stim);
+    g->G = g->Gn = g->Bp = g->stim = nullptr;
+}
+
+// Device buffers of one golden trace and its uploaded stimulus.
+static hipError_t alloc_golden(riros_golden g, const uint64_t* stimulus, hipStream_t s)
+{
+    const riros_design d = g->d;
+    const uint32_t T = g->T;
+    const size_t gbytes = (size_t)T * d->img.N * sizeof(uint64_t);
+    const size_t bpbytes = std::max<size_t>((size_t)d->img.bp_rows * ((T + 63) / 64), 1) * sizeof(uint64_t);
+    const size_t sbytes = std::max<size_t>((size_t)T * d->img.npi, 1) * sizeof(uint64_t);
+    hipError_t e = hipMalloc((void**)&g->G, gbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->Gn, gbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->Bp, bpbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->stim, sbytes);
+    if (e == hipSuccess && d->img.npi > 0)
+        e = hipMemcpyAsync(g->stim, stimulus, (size_t)T * d->img.npi * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    return e;
 }
 
 static void free_design_mem(riros_design d)
@@ -233,26 +257,65 @@ int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void*
     if (!g) return set_err(RIROS_ENOMEM, "host allocation failed");
     g->d = d;
     g->T = T;
-    const size_t gbytes = (size_t)T * d->img.N * sizeof(uint64_t);
-    const size_t bpbytes = std::max<size_t>((size_t)d->img.bp_rows * ((T + 63) / 64), 1) * sizeof(uint64_t);
-    const size_t sbytes = std::max<size_t>((size_t)T * d->img.npi, 1) * sizeof(uint64_t);
-    uint64_t* stim = nullptr;
-    hipError_t e = hipMalloc((void**)&g->G, gbytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&g->Gn, gbytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&g->Bp, bpbytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&stim, sbytes);
-    if (e == hipSuccess && d->img.npi > 0)
-        e = hipMemcpyAsync(stim, stimulus, (size_t)T * d->img.npi * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = riros::launch_golden(d->dev, stim, T, g->G, s);
+    hipError_t e = alloc_golden(g, stimulus, s);
+    if (e == hipSuccess) e = riros::launch_golden(d->dev, g->stim, T, g->G, s);
     if (e == hipSuccess) e = riros::launch_golden_layouts(d->dev, g->G, T, g->Gn, g->Bp, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (stim) (void)hipFree(stim);
     if (e != hipSuccess) {
         free_golden_mem(g);
         delete g;
         return hip_err(e, "golden simulation");
     }
     *out = g;
+    return RIROS_OK;
+}
+
+int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_t* const* stimulus, const uint32_t* T,
+                          void* stream, riros_golden* out)
+{
+    if (!designs || !stimulus || !T || !out) return set_err(RIROS_EINVAL, "NULL argument");
+    if (n == 0) return RIROS_OK;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!designs[i]) return set_err(RIROS_EINVAL, "design " + std::to_string(i) + " is NULL");
+        if (T[i] == 0) return set_err(RIROS_EINVAL, "design " + std::to_string(i) + ": T must be positive");
+        if (designs[i]->img.npi > 0 && !stimulus[i])
+            return set_err(RIROS_EINVAL, "design " + std::to_string(i) + ": stimulus is NULL");
+        if (designs[i]->device != designs[0]->device) return set_err(RIROS_EINVAL, "designs on different devices");
+    }
+    DeviceGuard guard(designs[0]->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<riros_golden> gs(n, nullptr);
+    std::vector<riros::DevDesign> td(n);
+    std::vector<riros::GoldenJob> jobs(n);
+    DevBuf<riros::DevDesign> dtd;
+    DevBuf<riros::GoldenJob> djobs;
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
+        gs[i] = new (std::nothrow) riros_golden_s();
+        if (!gs[i]) { e = hipErrorOutOfMemory; break; }
+        gs[i]->d = designs[i];
+        gs[i]->T = T[i];
+        e = alloc_golden(gs[i], stimulus[i], s);
+        td[i] = designs[i]->dev;
+        jobs[i] = riros::GoldenJob{gs[i]->stim, gs[i]->G, T[i]};
+    }
+    if (e == hipSuccess) e = dtd.alloc(n);
+    if (e == hipSuccess) e = djobs.alloc(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtd.p, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(djobs.p, jobs.data(), n * sizeof(riros::GoldenJob), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = riros::launch_golden_many(n, dtd.p, djobs.p, s);
+    for (uint32_t i = 0; i < n && e == hipSuccess; ++i)
+        e = riros::launch_golden_layouts(designs[i]->dev, gs[i]->G, T[i], gs[i]->Gn, gs[i]->Bp, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        for (riros_golden g : gs)
+            if (g) {
+                free_golden_mem(g);
+                delete g;
+            }
+        return hip_err(e, "golden simulation of many designs");
+    }
+    for (uint32_t i = 0; i < n; ++i) out[i] = gs[i];
     return RIROS_OK;
 }
 
@@ -334,9 +397,10 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         return set_err(RIROS_EINVAL, "unknown mode");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
-        !valid_share(opts->struct_share))
+        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg))
         return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, "
-                                     "light_cap not 0, 4, 8 or 16, or struct_share not 0, 1, 2 or 4)");
+                                     "light_cap not 0, 4, 8 or 16, struct_share not 0, 1, 2 or 4, or heavy_wg "
+                                     "not 0, 64, 128 or 256)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -450,6 +514,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.light_cap = opts->light_cap;
         p.unified = opts->unified;
         p.share = opts->struct_share;
+        p.heavy_wg = opts->heavy_wg > 0 ? opts->heavy_wg : 64;
         p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
@@ -662,7 +727,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         return set_err(RIROS_EINVAL, "campaigns run in RIROS_MODE_TWO_D with host-side inputs");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
-        !valid_share(opts->struct_share))
+        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg))
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
@@ -727,6 +792,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     uint64_t* d_ev = nullptr;
     uint64_t* d_wk = nullptr;
     riros_coverage* d_cov = nullptr;
+    riros::GoldenJob* d_jobs = nullptr;
     riros::Slot* d_slots = nullptr;
     uint64_t* d_regs = nullptr;
     uint64_t* d_stamp = nullptr;
@@ -745,12 +811,18 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     A(batch_alloc(b, &d_ev, b->F));
     A(batch_alloc(b, &d_wk, b->F));
     A(batch_alloc(b, &d_cov, n));
+    if (opts->campaign_golden) A(batch_alloc(b, &d_jobs, n));
     A(batch_alloc(b, &d_slots, (size_t)blocks * Nmax));
     A(batch_alloc(b, &d_regs, (size_t)blocks * 2 * std::max(Rmax, 1u)));
     A(batch_alloc(b, &d_stamp, 1));
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? RIROS_ENOMEM : RIROS_EDEVICE, "campaign allocation");
     A(hipMemcpy(d_td, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice));
     A(hipMemcpy(d_tg, tg.data(), n * sizeof(riros::GoldenView), hipMemcpyHostToDevice));
+    if (d_jobs) {
+        std::vector<riros::GoldenJob> jobs(n);
+        for (uint32_t i = 0; i < n; ++i) jobs[i] = riros::GoldenJob{goldens[i]->stim, goldens[i]->G, goldens[i]->T};
+        A(hipMemcpy(d_jobs, jobs.data(), n * sizeof(riros::GoldenJob), hipMemcpyHostToDevice));
+    }
     if (b->F) {
         A(hipMemcpy(d_fl, fl.data(), fl.size() * sizeof(riros_fault), hipMemcpyHostToDevice));
         A(hipMemcpy(d_did, did.data(), did.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
@@ -782,11 +854,12 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.words = d_wk;
     p.cov = d_cov;
     std::string err;
-    int rc = riros::order_batch(b->tw, d_pr, b->F, opts->theta, &p.order, b->cap_stream, err);
+    int rc = riros::order_batch(b->tw, d_pr, d_fl, b->F, opts->theta, &p.order, b->cap_stream, err);
     if (rc) return fail(rc, err);
     p.heavy = d_pr != nullptr && !(opts->theta > 3.0e38f);
     p.unified = opts->unified;
     p.share = opts->struct_share;
+    p.heavy_wg = opts->heavy_wg > 0 ? (uint32_t)opts->heavy_wg : 64u;
     p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);
@@ -794,7 +867,16 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     // Capture the run as a graph.
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = riros::launch_twod_batch(p, b->tw, b->cap_stream);
+        hipError_t le = hipSuccess;
+        if (d_jobs) {
+            // The golden machines of all designs (one workgroup each), then
+            // each trace's other layouts, then the fault simulation.
+            le = riros::launch_golden_many(n, d_td, d_jobs, b->cap_stream);
+            for (uint32_t i = 0; i < n && le == hipSuccess; ++i)
+                le = riros::launch_golden_layouts(designs[i]->dev, goldens[i]->G, goldens[i]->T, goldens[i]->Gn,
+                                                  goldens[i]->Bp, b->cap_stream);
+        }
+        if (le == hipSuccess) le = riros::launch_twod_batch(p, b->tw, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (le != hipSuccess) e = le;
     }

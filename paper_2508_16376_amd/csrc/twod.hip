@@ -402,8 +402,9 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     }
 }
 
-// Structural path for one fault, on the fault's design.
-template <bool BATCH>
+// Structural path for one fault, on the fault's design: one wavefront, or
+// (GROUP) every wavefront of the workgroup.
+template <bool BATCH, bool GROUP = false>
 __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, const riros_fault* __restrict__ faults,
                                           int drop, const WaveLds& s, Slot* slots, uint64_t* regs,
                                           uint64_t& stamp0, uint32_t* __restrict__ detect_out,
@@ -415,12 +416,13 @@ __device__ __forceinline__ void heavy_one(const DesignSrc& src, uint32_t fi, con
         const uint32_t k = src.did[fi];
         const DevDesign dd = src.td[k];
         const GoldenView gg = src.tg[k];
-        wave_sim_fault(dd, gg.G, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev, wk);
+        struct_sim_fault<GROUP>(dd, gg.G, gg.Gn, gg.Bp, gg.T, gg.TW, faults[fi], drop, s, slots, regs, stamp0, det, ev,
+                                wk);
     } else {
-        wave_sim_fault(src.d, src.g.G, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs, stamp0,
-                       det, ev, wk);
+        struct_sim_fault<GROUP>(src.d, src.g.G, src.g.Gn, src.g.Bp, src.g.T, src.g.TW, faults[fi], drop, s, slots, regs,
+                                stamp0, det, ev, wk);
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (GROUP ? threadIdx.x == 0 : (threadIdx.x & 63) == 0) {
         detect_out[fi] = det;
         if (events_out) events_out[fi] = ev;
         words_out[fi] = wk;
@@ -526,8 +528,8 @@ __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu
 void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
     const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-    uint32_t rate_num, int unified, uint32_t* __restrict__ detect_out, uint64_t* __restrict__ events_out,
-    uint64_t* __restrict__ words_out)
+    uint32_t rate_num, int unified, int group_heavy, uint32_t* __restrict__ detect_out,
+    uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     if constexpr (STRUCT) {
         extern __shared__ uint32_t lds[];
@@ -539,8 +541,19 @@ void k_twod_a(
         uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
         uint64_t stamp0 = *ws.stamp_dev;
         const uint32_t nh = ctr->n_heavy;
-        // Phase 1: heavy faults placed up front.
-        if (wave == 0) {
+        // Phase 1: heavy faults placed up front, each on every wavefront of
+        // the workgroup (group_heavy) or on its first wavefront.
+        if (group_heavy && blockDim.x > 64) {
+            for (;;) {
+                if (threadIdx.x == 0) s.flags[kFlagQueue] = atomicAdd(&ctr->heavy_head, 1u);
+                __syncthreads();
+                const uint32_t idx = s.flags[kFlagQueue];
+                __syncthreads();
+                if (idx >= nh) break;
+                heavy_one<BATCH, true>(src, order ? order[idx] : idx, faults, drop, s, slots, regs, stamp0, detect_out,
+                                       events_out, words_out);
+            }
+        } else if (wave == 0) {
             for (;;) {
                 uint32_t idx = 0;
                 if (threadIdx.x == 0) idx = atomicAdd(&ctr->heavy_head, 1u);
@@ -567,17 +580,22 @@ void k_twod_a(
     }
 }
 
-// Launch B: the faults handed over in launch A (their list is complete).
-// Stamps continue above the largest range launch A can have used (span).
-template <bool BATCH>
-__global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults,
-                                               TwoDCounters* ctr, const uint32_t* __restrict__ esc, int drop,
-                                               PlainWorkspace ws, uint64_t span, uint32_t* __restrict__ detect_out,
-                                               uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
+// Launch B: the faults handed over in launch A (their list is complete), one
+// per workgroup of 64 threads, or of 128 or 256 (GROUP: every wavefront of
+// the workgroup on the same fault).  Stamps continue above the largest range
+// launch A can have used (span).
+template <bool BATCH, bool GROUP>
+__global__ __launch_bounds__(GROUP ? 256 : 64) void k_twod_b(DesignSrc src, MaxShape mx,
+                                                            const riros_fault* __restrict__ faults,
+                                                            TwoDCounters* ctr, const uint32_t* __restrict__ esc,
+                                                            int drop, PlainWorkspace ws, uint64_t span,
+                                                            uint32_t* __restrict__ detect_out,
+                                                            uint64_t* __restrict__ events_out,
+                                                            uint64_t* __restrict__ words_out)
 {
     extern __shared__ uint32_t lds[];
     const WaveLds s = wave_lds_carve(lds, mx.N, mx.L, mx.R, mx.wpp);
-    wave_lds_clear(s, mx.N, mx.L, mx.R);
+    if (threadIdx.x < 64) wave_lds_clear(s, mx.N, mx.L, mx.R);
     __syncthreads();
     Slot* slots = ws.slots + (size_t)blockIdx.x * mx.N;
     uint64_t* regs = ws.regs + (size_t)blockIdx.x * 2 * mx.R;
@@ -585,21 +603,50 @@ __global__ __launch_bounds__(64) void k_twod_b(DesignSrc src, MaxShape mx, const
     const uint32_t n = ctr->esc_count;
     for (;;) {
         uint32_t idx = 0;
-        if (threadIdx.x == 0) idx = atomicAdd(&ctr->esc_head, 1u);
-        idx = __shfl(idx, 0, 64);
+        if constexpr (GROUP) {
+            if (threadIdx.x == 0) s.flags[kFlagQueue] = atomicAdd(&ctr->esc_head, 1u);
+            __syncthreads();
+            idx = s.flags[kFlagQueue];
+            __syncthreads();
+        } else {
+            if (threadIdx.x == 0) idx = atomicAdd(&ctr->esc_head, 1u);
+            idx = __shfl(idx, 0, 64);
+        }
         if (idx >= n) break;
         const uint32_t fi = esc[idx];
         if (fi == kDone) continue;   // simulated in launch A (phase 3)
-        heavy_one<BATCH>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out, words_out);
+        heavy_one<BATCH, GROUP>(src, fi, faults, drop, s, slots, regs, stamp0, detect_out, events_out, words_out);
     }
 }
 
 // Order: fault indexes sorted by descending priority; the prefix with
-// priority > theta is the up-front heavy queue.
+// priority > theta is the up-front heavy queue.  The sort key is
+//   bit 63      priority > theta (the heavy prefix stays exact),
+//   bits 32-62  the priority, ordered, with the low 19 bits of its IEEE
+//               pattern dropped (bands about 6% wide: the longest-first order
+//               is kept to that resolution),
+//   bits 0-31   the complement of the fault's site,
+// so that within a band faults on one node, and on nodes numbered together,
+// sit next to each other: a wavefront's lanes then take faults whose
+// frontiers walk the same nodes (the same records and golden lines, and the
+// same branches).
 __global__ void k_iota(uint32_t* __restrict__ v, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] = i;
+}
+
+__global__ void k_order_keys(const float* __restrict__ priority, const riros_fault* __restrict__ faults, uint32_t n,
+                             float theta, uint64_t* __restrict__ keys, uint32_t* __restrict__ idx)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float p = priority[i];
+    uint32_t u = __float_as_uint(p);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // IEEE order as unsigned order
+    const uint64_t heavy = p > theta ? 1ull : 0ull;
+    keys[i] = (heavy << 63) | ((uint64_t)(u >> 19) << 32) | (uint64_t)(~faults[i].site);
+    idx[i] = i;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ v, uint32_t n, uint32_t x)
@@ -608,12 +655,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ v, uint32_t n, uint32_t x)
     if (i < n) v[i] = x;
 }
 
-__global__ void k_count_heavy(const float* __restrict__ sorted_desc, uint32_t n, float theta, TwoDCounters* ctr)
+__global__ void k_count_heavy(const uint64_t* __restrict__ sorted_desc, uint32_t n, TwoDCounters* ctr)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const bool h = sorted_desc[i] > theta;
-        const bool next_h = (i + 1 < n) && sorted_desc[i + 1] > theta;
+        const bool h = (sorted_desc[i] >> 63) != 0;
+        const bool next_h = (i + 1 < n) && (sorted_desc[i + 1] >> 63) != 0;
         if (h && !next_h) ctr->n_heavy = i + 1;
     }
 }
@@ -680,7 +727,7 @@ __global__ __launch_bounds__(256) void k_batch_coverage(const uint32_t* __restri
 }
 
 struct TwoDLayout {
-    size_t ctr, esc, order, idx, keys_out, temp, total;
+    size_t ctr, esc, order, idx, keys_in, keys_out, temp, total;
     size_t temp_bytes;
 };
 
@@ -693,7 +740,8 @@ static TwoDLayout layout_for(uint32_t F, size_t temp_bytes)
     l.esc = o; o += up(((size_t)F + kTicketPad) * 4);
     l.order = o; o += up((size_t)F * 4);
     l.idx = o; o += up((size_t)F * 4);
-    l.keys_out = o; o += up((size_t)F * 4);
+    l.keys_in = o; o += up((size_t)F * 8);
+    l.keys_out = o; o += up((size_t)F * 8);
     l.temp = o; o += up(temp_bytes);
     l.total = o;
     l.temp_bytes = temp_bytes;
@@ -771,15 +819,36 @@ static GridA twod_grid_a(int cap, bool batch, bool structural, const MaxShape& m
     return g;
 }
 
+// Launch B's kernel for a structural workgroup of `wg` threads (64 = one
+// wavefront per fault).
+template <bool BATCH>
+static const void* kernel_b(uint32_t wg)
+{
+    return wg > 64 ? (const void*)k_twod_b<BATCH, true> : (const void*)k_twod_b<BATCH, false>;
+}
+
+template <bool BATCH>
+static void launch_b(uint32_t wg, uint32_t blocks, size_t lds, hipStream_t s, const DesignSrc& src,
+                     const MaxShape& mx, const riros_fault* faults, TwoDCounters* ctr, const uint32_t* esc, int drop,
+                     const PlainWorkspace& ws, uint64_t span, uint32_t* detect, uint64_t* events, uint64_t* words)
+{
+    if (wg > 64)
+        hipLaunchKernelGGL((k_twod_b<BATCH, true>), dim3(blocks), dim3(wg), lds, s, src, mx, faults, ctr, esc, drop,
+                           ws, span, detect, events, words);
+    else
+        hipLaunchKernelGGL((k_twod_b<BATCH, false>), dim3(blocks), dim3(64), lds, s, src, mx, faults, ctr, esc, drop,
+                           ws, span, detect, events, words);
+}
+
 template <int C, bool BATCH>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
-                                const uint32_t* order, bool heavy, int unified, int share, TwoDCounters* ctr,
-                                uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span, uint32_t blocks,
-                                uint32_t rate_num, uint32_t* detect, uint64_t* events, uint64_t* words,
-                                hipStream_t s)
+                                const uint32_t* order, bool heavy, int unified, int share, uint32_t heavy_wg,
+                                TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
+                                uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
+                                uint64_t* words, hipStream_t s)
 {
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
-    hipError_t e = hipFuncSetAttribute((const void*)k_twod_b<BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute(kernel_b<BATCH>(heavy_wg), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)ldsb);
     if (e != hipSuccess) return e;
     const bool structural = heavy || unified;
@@ -788,14 +857,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
-                           order, ctr, esc, drop, ws, rate_num, unified, detect, events, words);
+                           order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, detect, events, words);
     } else {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
-                           ctr, esc, drop, ws, rate_num, 0, detect, events, words);
+                           ctr, esc, drop, ws, rate_num, 0, 0, detect, events, words);
     }
-    const uint32_t bb = resident_blocks((const void*)k_twod_b<BATCH>, ldsb, blocks);
-    hipLaunchKernelGGL((k_twod_b<BATCH>), dim3(bb), dim3(64), ldsb, s, src, mx, faults, ctr, esc, drop, ws, span,
-                       detect, events, words);
+    const uint32_t wgb = heavy_wg > 64 ? heavy_wg : 64u;
+    const uint32_t bb = resident_blocks(kernel_b<BATCH>(wgb), ldsb, blocks, wgb);
+    launch_b<BATCH>(wgb, bb, ldsb, s, src, mx, faults, ctr, esc, drop, ws, span, detect, events, words);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_advance_stamp(ws.stamp_dev, 2 * span, s);
@@ -804,33 +873,35 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 template <bool BATCH>
 static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
                                   uint32_t F, const uint32_t* order, bool heavy, int unified, int share,
-                                  TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
-                                  uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
-                                  uint64_t* words, hipStream_t s)
+                                  uint32_t heavy_wg, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                  const PlainWorkspace& ws, uint64_t span, uint32_t blocks, uint32_t rate_num,
+                                  uint32_t* detect, uint64_t* events, uint64_t* words, hipStream_t s)
 {
     switch (cap) {
-    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
-    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
-    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
     }
 }
 
 // Ordering by priority (descending) and the heavy prefix count; outside any
 // graph (the sort may use library-internal memory operations).
-static int order_by_priority(TwoDWorkspace& ws, const TwoDLayout& lay, const float* priority, uint32_t F,
-                             float theta, TwoDCounters* ctr, hipStream_t s, std::string& err)
+static int order_by_priority(TwoDWorkspace& ws, const TwoDLayout& lay, const float* priority,
+                             const riros_fault* faults, uint32_t F, float theta, TwoDCounters* ctr, hipStream_t s,
+                             std::string& err)
 {
     char* base = (char*)ws.mem;
     uint32_t* idx = (uint32_t*)(base + lay.idx);
-    float* keys_out = (float*)(base + lay.keys_out);
+    uint64_t* keys_in = (uint64_t*)(base + lay.keys_in);
+    uint64_t* keys_out = (uint64_t*)(base + lay.keys_out);
     uint32_t* order = (uint32_t*)(base + lay.order);
-    hipLaunchKernelGGL(k_iota, dim3((F + 255) / 256), dim3(256), 0, s, idx, F);
+    hipLaunchKernelGGL(k_order_keys, dim3((F + 255) / 256), dim3(256), 0, s, priority, faults, F, theta, keys_in, idx);
     size_t tb = lay.temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, priority, keys_out, idx, order,
-                                                               (int)F, 0, 32, s);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, keys_in, keys_out, idx, order,
+                                                               (int)F, 0, 64, s);
     if (e != hipSuccess) { err = "priority sort failed"; return RIROS_EDEVICE; }
     if (!(theta > 3.0e38f))
-        hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, theta, ctr);
+        hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, ctr);
     return RIROS_OK;
 }
 
@@ -839,9 +910,9 @@ static int ensure_twod_ws(TwoDWorkspace& ws, uint32_t F, bool with_sort, TwoDLay
 {
     size_t temp_bytes = 0;
     if (with_sort) {
-        hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, temp_bytes, (const float*)nullptr,
-                                                                   (float*)nullptr, (const uint32_t*)nullptr,
-                                                                   (uint32_t*)nullptr, (int)F, 0, 32, s);
+        hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, temp_bytes, (const uint64_t*)nullptr,
+                                                                   (uint64_t*)nullptr, (const uint32_t*)nullptr,
+                                                                   (uint32_t*)nullptr, (int)F, 0, 64, s);
         if (e != hipSuccess) { err = "sort size query failed"; return RIROS_EDEVICE; }
     }
     lay = layout_for(F, temp_bytes);
@@ -871,7 +942,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
     const uint32_t* order = nullptr;
     if (priority) {
-        rc = order_by_priority(ws, lay, priority, F, p.theta, ctr, s, err);
+        rc = order_by_priority(ws, lay, priority, faults, F, p.theta, ctr, s, err);
         if (rc) return rc;
         order = (const uint32_t*)(base + lay.order);
     }
@@ -880,8 +951,9 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const MaxShape mx{d.N, d.L, d.R, words_per_pass(d.N, d.L, d.R, (uint32_t)std::max(1, p.waves_per_cu))};
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
-    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share, ctr, esc,
-                                          drop, heavy_ws, span, blocks, rate_num, detect, events, words, s);
+    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share,
+                                          (uint32_t)p.heavy_wg, ctr, esc, drop, heavy_ws, span, blocks, rate_num,
+                                          detect, events, words, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
     return RIROS_OK;
@@ -897,18 +969,20 @@ hipError_t prepare_twod_batch(BatchPlan& b)
     attr((const void*)k_twod_a<4, true, true>, lds_bytes_a(mx));
     attr((const void*)k_twod_a<8, true, true>, lds_bytes_a(mx));
     attr((const void*)k_twod_a<16, true, true>, lds_bytes_a(mx));
-    attr((const void*)k_twod_b<true>, lds_bytes_b(mx));
+    attr((const void*)k_twod_b<true, false>, lds_bytes_b(mx));
+    attr((const void*)k_twod_b<true, true>, lds_bytes_b(mx));
     if (e == hipSuccess) {
         const GridA ga = twod_grid_a(b.light_cap, true, b.heavy || b.unified, mx, b.blocks, b.share);
         b.blocks_a = ga.blocks;
         b.threads_a = ga.threads;
-        b.blocks_b = resident_blocks((const void*)k_twod_b<true>, lds_bytes_b(mx), b.blocks);
+        const uint32_t wgb = b.heavy_wg > 64 ? b.heavy_wg : 64u;
+        b.blocks_b = resident_blocks(kernel_b<true>(wgb), lds_bytes_b(mx), b.blocks, wgb);
     }
     return e;
 }
 
-int order_batch(TwoDWorkspace& ws, const float* priority, uint32_t F, float theta, const uint32_t** order,
-                hipStream_t s, std::string& err)
+int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta,
+                const uint32_t** order, hipStream_t s, std::string& err)
 {
     TwoDLayout lay;
     int rc = ensure_twod_ws(ws, F, priority != nullptr, lay, err, s);
@@ -918,7 +992,7 @@ int order_batch(TwoDWorkspace& ws, const float* priority, uint32_t F, float thet
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
     *order = nullptr;
     if (priority) {
-        rc = order_by_priority(ws, lay, priority, F, theta, ctr, s, err);
+        rc = order_by_priority(ws, lay, priority, faults, F, theta, ctr, s, err);
         if (rc) return rc;
         *order = (const uint32_t*)(base + lay.order);
     }
@@ -938,7 +1012,8 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
 #define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,     \
                        b.faults, b.F, b.order,                                                                   \
-                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.detect, b.events, b.words)
+                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0, b.detect, b.events,   \
+                       b.words)
     if (b.unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((b.F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, b.F + kTicketPad,
                            kNone);
@@ -956,8 +1031,8 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
         }
     }
 #undef RIROS_LAUNCH_A
-    hipLaunchKernelGGL((k_twod_b<true>), dim3(b.blocks_b), dim3(64), ldsb, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
-                       b.span, b.detect, b.events, b.words);
+    launch_b<true>(b.heavy_wg > 64 ? b.heavy_wg : 64u, b.blocks_b, ldsb, s, src, mx, b.faults, ctr, esc, b.drop, b.ws,
+                   b.span, b.detect, b.events, b.words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_advance_stamp(b.ws.stamp_dev, 2 * b.span, s);

@@ -23,6 +23,7 @@ struct TwoDParams {
     int light_cap = 0;
     int unified = 0;            // waves out of light work take handed-over faults during launch A
     int share = 0;              // launch A wavefronts per structural workspace (0 = as the LDS needs)
+    int heavy_wg = 64;          // threads that simulate one structural fault (64, 128 or 256)
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -61,6 +62,7 @@ struct BatchPlan {
     bool heavy = false;       // a heavy prefix exists (priorities with a finite threshold)
     int unified = 0;          // phase 3 in launch A (see riros_sim_opts.unified)
     int share = 0;            // launch A wavefronts per structural workspace (see riros_sim_opts.struct_share)
+    uint32_t heavy_wg = 64;   // threads per structural fault (see riros_sim_opts.heavy_wg)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;
@@ -78,10 +80,11 @@ struct BatchPlan {
 
 // Kernel attributes (outside any capture).
 hipError_t prepare_twod_batch(BatchPlan& b);
-// Order the concatenated faults by priority (NULL: keep them in order); sets
-// the heavy prefix.  Not capturable.
-int order_batch(TwoDWorkspace& ws, const float* priority, uint32_t F, float theta, const uint32_t** order,
-                hipStream_t s, std::string& err);
+// Order the concatenated faults by priority (NULL: keep them in order), faults
+// of one site together within a priority band; sets the heavy prefix.  Not
+// capturable.
+int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta,
+                const uint32_t** order, hipStream_t s, std::string& err);
 // The capturable part of a campaign run: counter reset, launches A and B,
 // stamp advance, per-design coverage.  ws must have been prepared by order_batch.
 hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t s);

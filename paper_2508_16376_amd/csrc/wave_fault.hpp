@@ -1,6 +1,7 @@
-// One faulty machine simulated by one wavefront, the divergent frontier of
-// each level split across the 64 lanes (structural parallelism of the paper,
-// Sec. IV-C, applied to a single fault).
+// One faulty machine simulated by one wavefront, or by a whole workgroup of
+// two or four wavefronts, the divergent frontier of each level split across
+// their lanes (the structural parallelism of the paper, Sec. IV-C, applied to
+// a single fault: one fault's load spread over many workers).
 #pragma once
 
 #include "device_common.hpp"
@@ -18,13 +19,17 @@ constexpr uint32_t kWordsWide = 64, kWordsNarrow = 16;
 // never advance).
 __host__ __device__ constexpr uint32_t norm_wpp(uint32_t wpp) { return wpp == kWordsWide ? kWordsWide : kWordsNarrow; }
 
-// LDS of one wave: sched[N/32] nodes to
-// evaluate this cycle, with ssum one bit per non-empty sched word (a sparse
-// frontier in a wide level is found without scanning the level's words);
-// lvlm[L/32] levels holding scheduled nodes; rcur/rnext[R/32] registers whose
-// state diverges in this / the next cycle, with summaries rcsum/rnsum;
-// list[32 * wpp] compacted node ids; flags; lvloff[L+1] the design's level
-// offsets (read once per fault, not per level).
+// LDS of one structural workspace (a wavefront, or a workgroup that runs one
+// fault): sched[N/32] nodes to evaluate this cycle, with ssum one bit per
+// non-empty sched word (a sparse frontier in a wide level is found without
+// scanning the level's words); lvlm[L/32] levels holding scheduled nodes;
+// rcur/rnext[R/32] registers whose state diverges in this / the next cycle,
+// with summaries rcsum/rnsum; list[32 * wpp] compacted node ids; flags[8]
+// (an output was divergent, then the values a workgroup's first wavefront
+// hands to the others); lvloff[L+1] the design's level offsets (read once per
+// fault, not per level).
+constexpr uint32_t kFlagWords = 8;
+enum : uint32_t { kFlagPo = 0, kFlagAnyReg, kFlagLevel, kFlagWord, kFlagTotal, kFlagQueue };
 struct WaveLds {
     uint32_t* sched;
     uint32_t* ssum;
@@ -42,8 +47,8 @@ struct WaveLds {
 __host__ __device__ inline size_t wave_lds_words(uint32_t N, uint32_t L, uint32_t R, uint32_t wpp)
 {
     const size_t W = (N + 31) / 32, WR = (R + 31) / 32;
-    return W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + 32 * (size_t)norm_wpp(wpp) + 4 +
-           (L + 1);
+    return W + (W + 31) / 32 + (L + 31) / 32 + 2 * WR + 2 * ((WR + 31) / 32) + 32 * (size_t)norm_wpp(wpp) +
+           kFlagWords + (L + 1);
 }
 
 // Words per pass for a design: the wide pass unless its LDS would keep fewer
@@ -68,7 +73,7 @@ __device__ inline WaveLds wave_lds_carve(uint32_t* base, uint32_t N, uint32_t L,
     s.rnsum = s.rcsum + (WR + 31) / 32;
     s.list = s.rnsum + (WR + 31) / 32;
     s.flags = s.list + 32 * norm_wpp(wpp);
-    s.lvloff = s.flags + 4;
+    s.lvloff = s.flags + kFlagWords;
     s.wpp = norm_wpp(wpp);
     return s;
 }
@@ -83,21 +88,42 @@ __device__ inline void wave_lds_clear(const WaveLds& s, uint32_t N, uint32_t L, 
     for (uint32_t i = lane; i < b; i += 64) s.rcur[i] = 0;
 }
 
+// Orders the LDS (and workgroup-local global) accesses of the lanes that run
+// one fault: a wave-level fence for one wavefront (other wavefronts of its
+// workgroup may run other work), a workgroup barrier for a whole workgroup.
+template <bool GROUP>
+__device__ __forceinline__ void struct_sync()
+{
+    if constexpr (GROUP) __syncthreads();
+    else wave_lds_sync();
+}
+
 // Simulate fault f from cycle 0 (drop: stop after the detect cycle).  slots
-// is this wave's [N] faulty-value array, regs its [2][R] register next-state
-// ping-pong; stamp0 advances by T.  Returns the detect cycle (uniform), the
-// event count and the byte-model words (wave totals; the words count each
-// event's NodeRec::words, a register event with divergent state twice, and
-// the site's golden word once per simulated cycle).  Must be called by all 64 lanes of one
-// wavefront; other wavefronts of its workgroup may run other work (it orders
-// its LDS accesses with wave_lds_sync, never a workgroup barrier).
-__device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gr,
-                                      const uint64_t* __restrict__ Gn,
-                                      const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
-                                      const riros_fault f, int drop, const WaveLds& s,
-                                      Slot* __restrict__ slots, uint64_t* __restrict__ regs,
-                                      uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out,
-                                      uint64_t& words_out)
+// is the workspace's [N] faulty-value array, regs its [2][R] register
+// next-state ping-pong; stamp0 advances by T.  Returns the detect cycle
+// (uniform), the event count and the byte-model words (totals over the
+// lanes; the words count each event's NodeRec::words, a register event with
+// divergent state twice, and the site's golden word once per simulated
+// cycle).
+//
+// GROUP = false: called by all 64 lanes of one wavefront; other wavefronts
+// of its workgroup may run other work (LDS accesses are ordered with
+// wave_lds_sync, never a workgroup barrier).
+// GROUP = true: called by every thread of the workgroup (2 or 4 wavefronts).
+// The first wavefront keeps the schedule (register sets, level and word
+// search, compaction of each pass) and hands its decisions to the others
+// through flags; every pass's frontier is then evaluated by all the
+// workgroup's lanes, with a barrier after it.  Every loop bound the threads
+// test is read after a barrier from the same LDS word, so all threads reach
+// the same barriers.
+template <bool GROUP>
+__device__ inline void struct_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gr,
+                                        const uint64_t* __restrict__ Gn,
+                                        const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
+                                        const riros_fault f, int drop, const WaveLds& s,
+                                        Slot* __restrict__ slots, uint64_t* __restrict__ regs,
+                                        uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out,
+                                        uint64_t& words_out)
 {
     // The LDS arrays as local values rather than fields read through a
     // reference: code that chooses between two of them then selects
@@ -117,48 +143,68 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
     const uint32_t R = d.R;
     const uint32_t WL = (d.L + 31) / 32, WR = (R + 31) / 32, WRS = (WR + 31) / 32;
     const uint32_t lane = threadIdx.x & 63;
+    // Thread index and count among the lanes that run this fault; lead: the
+    // wavefront that keeps the schedule.
+    const uint32_t gtid = GROUP ? threadIdx.x : lane;
+    const uint32_t gsize = GROUP ? blockDim.x : 64u;
+    const bool lead = GROUP ? threadIdx.x < 64 : true;
     const uint32_t site = d.u2i[f.site];
     const uint32_t site_lvl = d.level[site];
     const uint32_t fbit = f.bit, fval = f.stuck, ft0 = f.t0;
     const uint64_t* __restrict__ srow = Bp + (size_t)(d.bp_off[site] + fbit) * TW;   // the site bit, 64 cycles a word
-    // Register state left by the previous fault on this wave: clear the words
-    // the summaries point at.
-    for (uint32_t j = lane; j < WRS; j += 64) {
-        for (uint32_t m = rcsum[j]; m; m &= m - 1) rcur[j * 32 + __ffs(m) - 1] = 0;
-        for (uint32_t m = rnsum[j]; m; m &= m - 1) rnext[j * 32 + __ffs(m) - 1] = 0;
-        rcsum[j] = 0;
-        rnsum[j] = 0;
-    }
-    for (uint32_t i = lane; i <= d.L; i += 64) lvloff[i] = d.lvl_off[i];
-    uint32_t ev = 0, wk = 0;
-    uint32_t det = RIROS_UNDETECTED;
-    wave_lds_sync();
-    for (uint32_t t = 0; t < T; ++t) {
-        // Cycle start: registers whose D diverged last cycle are scheduled.
-        // Lane j owns summary word j, hence register words 32j..32j+31 and
-        // the sched summary word j (registers have the lowest ids).
-        uint32_t any = 0;
+    // Register state left by the previous fault on this workspace: clear the
+    // words the summaries point at.
+    if (lead) {
         for (uint32_t j = lane; j < WRS; j += 64) {
             for (uint32_t m = rcsum[j]; m; m &= m - 1) rcur[j * 32 + __ffs(m) - 1] = 0;
-            const uint32_t nm = rnsum[j];
-            for (uint32_t m = nm; m; m &= m - 1) {
-                const uint32_t i = j * 32 + __ffs(m) - 1;
-                const uint32_t v = rnext[i];
-                rcur[i] = v;
-                rnext[i] = 0;
-                sched[i] |= v;
-                any |= v;
-            }
-            rcsum[j] = nm;
+            for (uint32_t m = rnsum[j]; m; m &= m - 1) rnext[j * 32 + __ffs(m) - 1] = 0;
+            rcsum[j] = 0;
             rnsum[j] = 0;
-            ssum[j] |= nm;
         }
-        const bool anyreg = __ballot(any != 0) != 0;
+    }
+    for (uint32_t i = gtid; i <= d.L; i += gsize) lvloff[i] = d.lvl_off[i];
+    uint32_t ev = 0, wk = 0;
+    uint32_t det = RIROS_UNDETECTED;
+    struct_sync<GROUP>();
+    for (uint32_t t = 0; t < T; ++t) {
+        // Cycle start: registers whose D diverged last cycle are scheduled.
+        // Lane j of the lead wavefront owns summary word j, hence register
+        // words 32j..32j+31 and the sched summary word j (registers have the
+        // lowest ids).
+        uint32_t any = 0;
+        if (lead) {
+            for (uint32_t j = lane; j < WRS; j += 64) {
+                for (uint32_t m = rcsum[j]; m; m &= m - 1) rcur[j * 32 + __ffs(m) - 1] = 0;
+                const uint32_t nm = rnsum[j];
+                for (uint32_t m = nm; m; m &= m - 1) {
+                    const uint32_t i = j * 32 + __ffs(m) - 1;
+                    const uint32_t v = rnext[i];
+                    rcur[i] = v;
+                    rnext[i] = 0;
+                    sched[i] |= v;
+                    any |= v;
+                }
+                rcsum[j] = nm;
+                rnsum[j] = 0;
+                ssum[j] |= nm;
+            }
+        }
+        bool anyreg;
+        if constexpr (GROUP) {
+            if (lead) {
+                const bool b = __ballot(any != 0) != 0;
+                if (lane == 0) flags[kFlagAnyReg] = b ? 1u : 0u;
+            }
+            struct_sync<GROUP>();
+            anyreg = flags[kFlagAnyReg] != 0;
+        } else {
+            anyreg = __ballot(any != 0) != 0;
+        }
         if (!anyreg) {
             // No divergent state: the machine equals the golden one until the
             // site is next excited (its golden bit differs from the stuck
             // value; a flip, only in its cycle), so jump there; no event and
-            // no detection in between.
+            // no detection in between.  Every thread reads the same words.
             bool found = false;
             if (fval == RIROS_FAULT_FLIP) {
                 found = t <= ft0 && ft0 < T;
@@ -183,32 +229,39 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
         const uint64_t stamp = stamp0 + t + 1;
         const uint64_t* rst = regs + (size_t)(t & 1) * R;
         uint64_t* rnx = regs + (size_t)((t + 1) & 1) * R;
-        if (lane == 0) flags[0] = 0;
-        wave_lds_sync();
-        if (lane == 0) {
+        if (gtid == 0) flags[kFlagPo] = 0;
+        struct_sync<GROUP>();
+        if (gtid == 0) {
             sched[site >> 5] |= 1u << (site & 31);
             ssum[site >> 10] |= 1u << ((site >> 5) & 31);
             lvlm[site_lvl >> 5] |= 1u << (site_lvl & 31);
             if (anyreg) lvlm[0] |= 1u;
         }
-        wave_lds_sync();
+        struct_sync<GROUP>();
         for (;;) {
             // Lowest level with scheduled nodes (users are always at higher levels).
             int lv = -1;
-            for (uint32_t wb = 0; wb < WL; wb += 64) {
-                const uint32_t w = wb + lane;
-                const uint32_t m = w < WL ? lvlm[w] : 0u;
-                const uint64_t bal = __ballot(m != 0);
-                if (bal) {
-                    const int first = __ffsll((unsigned long long)bal) - 1;
-                    const uint32_t mw = __shfl(m, first, 64);
-                    lv = (int)((wb + first) * 32 + __ffs(mw) - 1);
-                    break;
+            if (lead) {
+                for (uint32_t wb = 0; wb < WL; wb += 64) {
+                    const uint32_t w = wb + lane;
+                    const uint32_t m = w < WL ? lvlm[w] : 0u;
+                    const uint64_t bal = __ballot(m != 0);
+                    if (bal) {
+                        const int first = __ffsll((unsigned long long)bal) - 1;
+                        const uint32_t mw = __shfl(m, first, 64);
+                        lv = (int)((wb + first) * 32 + __ffs(mw) - 1);
+                        break;
+                    }
                 }
             }
+            if constexpr (GROUP) {
+                if (gtid == 0) flags[kFlagLevel] = (uint32_t)lv;
+                struct_sync<GROUP>();
+                lv = (int)flags[kFlagLevel];
+            }
             if (lv < 0) break;
-            wave_lds_sync();
-            if (lane == 0) lvlm[lv >> 5] &= ~(1u << (lv & 31));
+            struct_sync<GROUP>();
+            if (gtid == 0) lvlm[lv >> 5] &= ~(1u << (lv & 31));
             const uint32_t lo = lvloff[lv], hi = lvloff[lv + 1];
             const uint32_t w0 = lo >> 5, w1 = (hi - 1) >> 5, s1 = w1 >> 5;
             uint32_t wb = w0;
@@ -216,24 +269,32 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 // Next non-empty sched word at or after wb, from the summary
                 // (64 summary words, 65,536 nodes, per probe).
                 uint32_t nw = 0xFFFFFFFFu;
-                for (uint32_t sb = wb >> 5; sb <= s1; sb += 64) {
-                    const uint32_t sw = sb + lane;
-                    uint32_t sm = sw <= s1 ? ssum[sw] : 0u;
-                    if (sw == (wb >> 5)) sm &= ~0u << (wb & 31);
-                    const uint64_t bal = __ballot(sm != 0);
-                    if (bal) {
-                        const int first = __ffsll((unsigned long long)bal) - 1;
-                        const uint32_t mw = __shfl(sm, first, 64);
-                        nw = (sb + (uint32_t)first) * 32 + (uint32_t)(__ffs(mw) - 1);
-                        break;
+                if (lead) {
+                    for (uint32_t sb = wb >> 5; sb <= s1; sb += 64) {
+                        const uint32_t sw = sb + lane;
+                        uint32_t sm = sw <= s1 ? ssum[sw] : 0u;
+                        if (sw == (wb >> 5)) sm &= ~0u << (wb & 31);
+                        const uint64_t bal = __ballot(sm != 0);
+                        if (bal) {
+                            const int first = __ffsll((unsigned long long)bal) - 1;
+                            const uint32_t mw = __shfl(sm, first, 64);
+                            nw = (sb + (uint32_t)first) * 32 + (uint32_t)(__ffs(mw) - 1);
+                            break;
+                        }
                     }
+                }
+                if constexpr (GROUP) {
+                    if (gtid == 0) flags[kFlagWord] = nw;
+                    struct_sync<GROUP>();
+                    nw = flags[kFlagWord];
                 }
                 if (nw > w1) break;
                 wb = nw;
-                // Words wb..wb+wpp-1 of this level: one per lane.
+                // Words wb..wb+wpp-1 of this level: one per lane of the lead
+                // wavefront, compacted into list.
                 const uint32_t w = wb + lane;
                 uint32_t bits = 0;
-                if (lane < wpp && w <= w1) {
+                if (lead && lane < wpp && w <= w1) {
                     uint32_t m = ~0u;
                     if (w == w0) m &= ~0u << (lo & 31);
                     if (w == w1 && (hi & 31)) m &= (1u << (hi & 31)) - 1u;
@@ -245,17 +306,36 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                     }
                 }
                 wb += wpp;
-                if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
-                const uint32_t cnt = __popc(bits);
-                const uint32_t incl = wave_incl_scan(cnt);
-                const uint32_t total = __shfl(incl, 63, 64);
-                uint32_t off = incl - cnt;
-                while (bits) {
-                    const int b = __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    list[off++] = w * 32 + (uint32_t)b;
+                uint32_t total = 0;
+                if constexpr (GROUP) {
+                    if (lead) {
+                        const uint32_t cnt = __popc(bits);
+                        const uint32_t incl = wave_incl_scan(cnt);
+                        total = __shfl(incl, 63, 64);
+                        uint32_t off = incl - cnt;
+                        while (bits) {
+                            const int b = __ffs(bits) - 1;
+                            bits &= bits - 1;
+                            list[off++] = w * 32 + (uint32_t)b;
+                        }
+                        if (lane == 0) flags[kFlagTotal] = total;
+                    }
+                    struct_sync<GROUP>();
+                    total = flags[kFlagTotal];
+                    if (total == 0) continue;   // only other levels' nodes in these words
+                } else {
+                    if (__ballot(bits != 0) == 0) continue;   // only other levels' nodes in these words
+                    const uint32_t cnt = __popc(bits);
+                    const uint32_t incl = wave_incl_scan(cnt);
+                    total = __shfl(incl, 63, 64);
+                    uint32_t off = incl - cnt;
+                    while (bits) {
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        list[off++] = w * 32 + (uint32_t)b;
+                    }
+                    wave_lds_sync();
                 }
-                wave_lds_sync();
                 // A dense pass (more nodes than lanes) reads golden values from
                 // the cycle-major trace, where a level's nodes are neighbours
                 // and the cycle's row is shared by every fault near that
@@ -263,7 +343,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                 // keeps its line for sixteen cycles.
                 const bool dense = total > 64;
                 auto goldp = [&](uint32_t n) { return dense ? Gr[(size_t)t * d.N + n] : Gn[(size_t)n * T + t]; };
-                for (uint32_t i = lane; i < total; i += 64) {
+                for (uint32_t i = gtid; i < total; i += gsize) {
                     const uint32_t n = list[i];
                     // Two dependent round trips per node: the record (descriptor + fan-out ranges,
                     // with the node's own golden value beside it), then everything the record
@@ -308,7 +388,7 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         sl.v = v;
                         sl.stamp = stamp;
                         slots[n] = sl;
-                        if (x.flags & DF_PO) flags[0] = 1;
+                        if (x.flags & DF_PO) flags[kFlagPo] = 1;
                         for (uint32_t e = x.fo0; e < x.fo1; ++e) {
                             const uint32_t k = e - x.fo0;
                             const uint64_t pk = k == 0 ? pk0 : k == 1 ? pk1 : k == 2 ? pk2 : k == 3 ? pk3 : d.fo_pk[e];
@@ -325,18 +405,49 @@ __device__ inline void wave_sim_fault(const DevDesign& d, const uint64_t* __rest
                         }
                     }
                 }
-                wave_lds_sync();
+                struct_sync<GROUP>();
             }
         }
-        if (flags[0] && det == RIROS_UNDETECTED) det = t;
-        wave_lds_sync();
+        if (flags[kFlagPo] && det == RIROS_UNDETECTED) det = t;
+        struct_sync<GROUP>();
         if (drop && det != RIROS_UNDETECTED) break;
     }
     stamp0 += T;
     det_out = det;
-    ev_out = wave_sum_u64((uint64_t)ev);
+    uint64_t evs = wave_sum_u64((uint64_t)ev), wks = wave_sum_u64((uint64_t)wk);
+    if constexpr (GROUP) {
+        // Sum the wavefronts' totals through the (idle) list array.
+        const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+        if (lane == 0) {
+            list[4 * wave] = (uint32_t)evs;
+            list[4 * wave + 1] = (uint32_t)(evs >> 32);
+            list[4 * wave + 2] = (uint32_t)wks;
+            list[4 * wave + 3] = (uint32_t)(wks >> 32);
+        }
+        __syncthreads();
+        evs = 0;
+        wks = 0;
+        for (uint32_t k = 0; k < nwaves; ++k) {
+            evs += make_u64(list[4 * k], list[4 * k + 1]);
+            wks += make_u64(list[4 * k + 2], list[4 * k + 3]);
+        }
+        __syncthreads();
+    }
+    ev_out = evs;
     const uint64_t cycles = (drop && det != RIROS_UNDETECTED) ? (uint64_t)det + 1u : (uint64_t)T;
-    words_out = wave_sum_u64((uint64_t)wk) + cycles * (d.uwidth[f.site] > 32 ? 2u : 1u);
+    words_out = wks + cycles * (d.uwidth[f.site] > 32 ? 2u : 1u);
+}
+
+// One fault on one wavefront.
+__device__ __forceinline__ void wave_sim_fault(const DevDesign& d, const uint64_t* __restrict__ Gr,
+                                               const uint64_t* __restrict__ Gn,
+                                               const uint64_t* __restrict__ Bp, uint32_t T, uint32_t TW,
+                                               const riros_fault f, int drop, const WaveLds& s,
+                                               Slot* __restrict__ slots, uint64_t* __restrict__ regs,
+                                               uint64_t& stamp0, uint32_t& det_out, uint64_t& ev_out,
+                                               uint64_t& words_out)
+{
+    struct_sim_fault<false>(d, Gr, Gn, Bp, T, TW, f, drop, s, slots, regs, stamp0, det_out, ev_out, words_out);
 }
 
 }  // namespace riros

@@ -31,7 +31,7 @@ EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
             "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad",
             "riros_batch_create", "riros_batch_launch", "riros_batch_read", "riros_batch_free",
-            "riros_peak_hbm", "riros_peak_valu"]
+            "riros_peak_hbm", "riros_peak_valu", "riros_golden_sim_many"]
 N_FEATURES = 6
 MLP_PARAMS = 4673
 MLP_WEIGHTS = MLP_PARAMS + 12
@@ -53,7 +53,8 @@ class SimOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("priority", ctypes.c_void_p), ("theta", ctypes.c_float),
                 ("light_cap", ctypes.c_int32), ("unified", ctypes.c_int32), ("monitor_rate", ctypes.c_float),
                 ("struct_share", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("words", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("words", ctypes.c_void_p), ("campaign_golden", ctypes.c_int32),
+                ("heavy_wg", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):
@@ -107,6 +108,8 @@ def lib():
         L.riros_free_design.restype = None
         L.riros_golden_sim.argtypes = [P, P, U, P, ctypes.POINTER(P)]
         L.riros_golden_sim.restype = I
+        L.riros_golden_sim_many.argtypes = [U, P, P, P, P, P]
+        L.riros_golden_sim_many.restype = I
         L.riros_free_golden.argtypes = [P]
         L.riros_free_golden.restype = None
         L.riros_golden_read.argtypes = [P, U, U, P]
@@ -196,15 +199,33 @@ class Design:
 class Golden:
     """riros_golden_sim handle (trace resident on the device)."""
 
-    def __init__(self, design: Design, stimulus: np.ndarray, T: int, stream=None):
+    def __init__(self, design: Design, stimulus: np.ndarray, T: int, stream=None, _handle=None):
+        self.design = design
+        self.T = T
+        if _handle is not None:
+            self.handle = _handle
+            return
         stim = np.ascontiguousarray(stimulus[:T], dtype=np.uint64)
         if stim.shape[0] < T:
             raise ValueError("stimulus has fewer rows than T")
         h = ctypes.c_void_p()
         _check(lib().riros_golden_sim(design.handle, _ptr(stim), T, _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
-        self.design = design
-        self.T = T
+
+    @staticmethod
+    def many(designs, stimuli, Ts, stream=None):
+        """riros_golden_sim_many: the golden traces of many designs in one launch."""
+        n = len(designs)
+        stims = [np.ascontiguousarray(s[:T], dtype=np.uint64) for s, T in zip(stimuli, Ts)]
+        for s_, T in zip(stims, Ts):
+            if s_.shape[0] < T:
+                raise ValueError("stimulus has fewer rows than T")
+        dh = (ctypes.c_void_p * n)(*[d.handle.value for d in designs])
+        sp = (ctypes.c_void_p * n)(*[s_.ctypes.data for s_ in stims])
+        Ta = np.ascontiguousarray(Ts, dtype=np.uint32)
+        out = (ctypes.c_void_p * n)()
+        _check(lib().riros_golden_sim_many(n, dh, sp, _ptr(Ta), _stream_ptr(stream), out))
+        return [Golden(d, None, int(T), _handle=ctypes.c_void_p(out[i])) for i, (d, T) in enumerate(zip(designs, Ts))]
 
     def read(self, t0: int = 0, nt: int | None = None) -> np.ndarray:
         nt = self.T - t0 if nt is None else nt
@@ -231,14 +252,15 @@ COVERAGE_FIELDS = 5
 
 def make_opts(mode=MODE_PLAIN, drop=True, io_on_device=False, waves_per_cu=0, priority=None,
               theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None, struct_share=0,
-              words=None) -> SimOpts:
+              words=None, campaign_golden=False, heavy_wg=0) -> SimOpts:
     return SimOpts(mode, 1 if drop else 0, 1 if io_on_device else 0, waves_per_cu, _ptr(priority),
-                   theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream), _ptr(words))
+                   theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream), _ptr(words),
+                   1 if campaign_golden else 0, heavy_wg)
 
 
 def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_PLAIN, drop=True,
               waves_per_cu=0, priority=None, theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0,
-              stream=None, with_events=True, struct_share=0, words_out=None):
+              stream=None, with_events=True, struct_share=0, words_out=None, heavy_wg=0):
     """riros_fault_sim on host arrays: returns (detect, events, coverage dict).
     words_out (optional uint64[F]) receives the per-fault byte-model words."""
     fl = np.ascontiguousarray(faults)
@@ -249,7 +271,7 @@ def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_P
     if words_out is not None:
         assert words_out.dtype == np.uint64 and words_out.size == F and words_out.flags.c_contiguous
     opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, unified, monitor_rate, stream,
-                     struct_share, words_out)
+                     struct_share, words_out, heavy_wg=heavy_wg)
     cov = Coverage()
     _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(fl), F, ctypes.byref(opts), _ptr(detect),
                                  _ptr(events), ctypes.byref(cov)))
@@ -327,7 +349,8 @@ class Batch:
     """riros_batch_create handle: a campaign of designs run as one graph launch."""
 
     def __init__(self, designs, goldens, fault_lists, priorities=None, *, drop=True, waves_per_cu=0,
-                 theta=math.inf, light_cap=0, monitor_rate=0.0, unified=0, struct_share=0):
+                 theta=math.inf, light_cap=0, monitor_rate=0.0, unified=0, struct_share=0, campaign_golden=False,
+                 heavy_wg=0):
         n = len(designs)
         fls = [np.ascontiguousarray(f) for f in fault_lists]
         self.F = [int(f.size) for f in fls]
@@ -342,7 +365,7 @@ class Batch:
             keep = prs
             pp = (ctypes.c_void_p * n)(*[0 if p is None else p.ctypes.data for p in prs])
         opts = make_opts(MODE_TWO_D, drop, False, waves_per_cu, None, theta, light_cap, unified, monitor_rate, None,
-                         struct_share)
+                         struct_share, campaign_golden=campaign_golden, heavy_wg=heavy_wg)
         h = ctypes.c_void_p()
         _check(lib().riros_batch_create(n, dh, gh, fp, _ptr(Fa), pp, ctypes.byref(opts), ctypes.byref(h)))
         del keep

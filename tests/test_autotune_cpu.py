@@ -10,12 +10,13 @@ def test_descent_finds_the_coordinatewise_minimum():
         c = abs(p["monitor_rate"] - 4.0) + (0 if p["light_cap"] == 4 else 1) + abs(p["waves_per_cu"] - 16) / 4
         c += 0 if p["heavy_quantile"] == 0.99 else 0.5
         c += 0 if p["unified"] == 0 else 0.25
+        c += 0 if p["heavy_wg"] == 128 else 0.125
         return c
 
     t = autotune.Autotuner()
     best, bt = t._descend(cost, with_priority=True)
     assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 1,
-                    "heavy_quantile": 0.99}
+                    "heavy_wg": 128, "heavy_quantile": 0.99}
     assert bt == 0
     # every candidate is a point of the space; the descent times no point
     # twice, and then the three fastest points are timed twice more each
@@ -62,3 +63,21 @@ def test_confirmation_ranks_by_mean_not_by_a_lucky_timing():
     assert best["monitor_rate"] == 4.0
     assert bt == 3.0
     assert lucky["monitor_rate"] != best["monitor_rate"]
+
+
+def test_budget_stops_the_descent_and_keeps_the_best_so_far():
+    """Once the wall budget is spent no new point is timed; the confirmation
+    of the fastest points still runs."""
+    import time
+    calls = []
+
+    def cost(p):
+        calls.append(dict(p))
+        time.sleep(0.02)
+        return 1.0 if p["monitor_rate"] == 1.0 else 2.0
+
+    t = autotune.Autotuner(budget_s=0.05)
+    best, _ = t._descend(cost, with_priority=True)
+    distinct = len({tuple(sorted(c.items(), key=lambda kv: kv[0])) for c in calls})
+    assert distinct <= 5
+    assert best["monitor_rate"] in (1.0, 2.0)

@@ -74,24 +74,6 @@ def test_campaign_equals_single_design_runs(small_campaign):
         np.testing.assert_array_equal(ev, sev)
 
 
-def test_full_size_campaign_sampled():
-    """The 64-design campaign at full size; per design, a sample of faults is
-    re-simulated by the oracle one by one, and coverage totals are consistent."""
-    ws = W.campaign()
-    ds, gs = _load(ws)
-    b = riros.Batch(ds, gs, [w.faults for w in ws], monitor_rate=2.0, unified=1)
-    b.launch()
-    for i, w in enumerate(ws):
-        det, ev, cov = b.read(i)
-        idx = np.linspace(0, w.faults.size - 1, min(60, w.faults.size)).astype(np.int64)
-        odet, oev = oracle.fault_sim(w.design, w.stimulus, w.T, w.faults[idx])
-        np.testing.assert_array_equal(det[idx], odet, err_msg=f"design {i}")
-        np.testing.assert_array_equal(ev[idx], oev, err_msg=f"design {i}")
-        assert cov["total"] == w.faults.size
-        assert cov["detected"] == int((det != riros.UNDETECTED).sum())
-        assert ((det < w.T) | (det == riros.UNDETECTED)).all()
-
-
 def test_campaign_with_flips():
     """Stuck-at faults and bit flips mixed in one campaign, on two replays."""
     ws = W.campaign(seed=515151, n=5, nodes=(300, 3000), faults=(200, 2000), cycles=(50, 300))
@@ -105,3 +87,36 @@ def test_campaign_with_flips():
             det, ev, _ = b.read(i)
             np.testing.assert_array_equal(det, refs[i][0])
             np.testing.assert_array_equal(ev, refs[i][1])
+
+
+def test_golden_many_equals_oracle(small_campaign):
+    """riros_golden_sim_many (one workgroup per design, one launch) gives each
+    design the oracle's golden trace."""
+    ws, _ = small_campaign
+    ds = [riros.Design(w.design) for w in ws]
+    gs = riros.Golden.many(ds, [w.stimulus for w in ws], [w.T for w in ws])
+    for w, g in zip(ws, gs):
+        np.testing.assert_array_equal(g.read(), oracle.golden(w.design, w.stimulus, w.T), err_msg=w.name)
+
+
+def test_campaign_golden_in_graph_on_every_replay(small_campaign):
+    """The campaign graph recomputes every golden trace before the fault
+    simulation (goldens from riros_golden_sim_many); three replays with
+    unrelated work between them all give the oracle's results."""
+    import torch
+    ws, refs = small_campaign
+    ds = [riros.Design(w.design) for w in ws]
+    gs = riros.Golden.many(ds, [w.stimulus for w in ws], [w.T for w in ws])
+    prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
+    b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=float(np.quantile(np.concatenate(prios), 0.9)),
+                    monitor_rate=2.0, unified=1, campaign_golden=True)
+    for rep in range(3):
+        b.launch()
+        torch.cuda.synchronize()
+        assert torch.ones(1 << 20, device="cuda").sum().item() == float(1 << 20)
+        for i, w in enumerate(ws):
+            det, ev, _ = b.read(i)
+            np.testing.assert_array_equal(det, refs[i][0], err_msg=f"replay {rep} design {i}")
+            np.testing.assert_array_equal(ev, refs[i][1], err_msg=f"replay {rep} design {i}")
+        np.testing.assert_array_equal(gs[0].read(), oracle.golden(ws[0].design, ws[0].stimulus, ws[0].T))
+    b.close()

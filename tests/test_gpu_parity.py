@@ -256,6 +256,38 @@ def test_two_d_shared_structural_workspace(small, share):
                theta=0.9, monitor_rate=2.0, unified=1, struct_share=share, waves_per_cu=wpc)
 
 
+@pytest.mark.parametrize("heavy_wg", [128, 256])
+def test_two_d_workgroup_structural_split(small, tiny, heavy_wg):
+    """A structural fault simulated by 2 or 4 wavefronts (the frontier of
+    each pass split across all their lanes, one barrier per pass): in launch
+    B for handed-over faults, and in launch A's heavy prefix when its
+    workgroups hold several wavefronts; drop on and off, every fault on the
+    structural path (theta -inf) or a prefix of them, small grids."""
+    prio = (W.counter_values(17, 0, small.faults.size) >> np.uint64(40)).astype(np.float32) / np.float32(1 << 24)
+    for drop in (True, False):
+        for share, theta, unified in ((1, float("inf"), 0), (2, float("-inf"), 0), (4, 0.7, 1), (2, 0.5, 1)):
+            _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, priority=prio,
+                   theta=theta, monitor_rate=1.0, light_cap=4, unified=unified, struct_share=share,
+                   heavy_wg=heavy_wg)
+    _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, True, priority=prio,
+           theta=0.5, monitor_rate=0.5, unified=0, struct_share=4, heavy_wg=heavy_wg, waves_per_cu=1)
+    tp = np.ones(tiny.faults.size, dtype=np.float32)
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, False, priority=tp,
+           theta=0.0, struct_share=4, heavy_wg=heavy_wg)
+
+
+def test_two_d_workgroup_split_medium_no_drop_sample():
+    """Dense faults (no dropping, the paper's convention): every fault of a
+    sample of the medium list on four-wavefront structural workgroups."""
+    w = W.medium()
+    idx = np.sort(np.argsort(W.counter_values(0xD0D0, 0, w.faults.size), kind="stable")[:100])
+    prio = np.ones(idx.size, dtype=np.float32)
+    _check(w.design, w.stimulus, w.T, w.faults[idx], riros.MODE_TWO_D, False, priority=prio, theta=0.0,
+           struct_share=4, heavy_wg=256, unified=1)
+    _check(w.design, w.stimulus, w.T, w.faults[idx], riros.MODE_TWO_D, False, light_cap=4, monitor_rate=0.5,
+           heavy_wg=256)
+
+
 def test_two_d_unified_medium_full_size():
     w = W.medium()
     _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, monitor_rate=2.0, light_cap=4, unified=1)
@@ -264,7 +296,8 @@ def test_two_d_unified_medium_full_size():
 def test_two_d_rejects_bad_options(tiny):
     d = riros.Design(tiny.design)
     g = riros.Golden(d, tiny.stimulus, tiny.T)
-    for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}, {"struct_share": 3}, {"struct_share": 8}):
+    for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}, {"struct_share": 3}, {"struct_share": 8},
+               {"heavy_wg": 96}, {"heavy_wg": 512}):
         with pytest.raises(riros.RirosError):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
