@@ -361,7 +361,15 @@ def main():
                     help="the 64-design batched campaign as a second measured leg (single-design workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one copy of known size (for scaling the HBM byte counters)")
+    ap.add_argument("--params", default=None,
+                    help="schedule parameters as JSON (the autotuner's output): no tuning")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="run only the timed predictor leg (for kernel traces and counters: every fault-"
+                         "simulation launch of the run is then one of the timed ones)")
     args = ap.parse_args()
+    if args.only_headline:
+        args.no_cpu_baseline = True
+        args.no_drop_leg = args.concurrent_leg = args.campaign_leg = "off"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the fault list across "
               "GPUs (by fault, with one final gather) is not implemented.", file=sys.stderr)
@@ -382,11 +390,15 @@ def main():
 
     # Plain fault-parallel kernel (K2).
     psteps = min(args.steps, PLAIN_STEPS)
-    if multi:
+    plain = None
+    if args.only_headline:
+        pass
+    elif multi:
         plain = job.run_plain(psteps, min(args.warmup, 1))
     else:
         plain = job.run(riros.MODE_PLAIN, psteps, min(args.warmup, 1), {})
-    log(f"[bench] plain: kernel {plain['kernel_ms']:.3f} ms, rate {rate(plain):.4g} FC/s")
+    if plain:
+        log(f"[bench] plain: kernel {plain['kernel_ms']:.3f} ms, rate {rate(plain):.4g} FC/s")
 
     # Predictor: trained on held-out designs' plain-kernel events.
     pred_info, preds, wts, feats = {}, None, None, None
@@ -396,20 +408,23 @@ def main():
         feats = job.features()
         preds = [riros.mlp_predict(wts, f) for f in feats] if multi else riros.mlp_predict(wts, feats)
         pred_info["features_and_inference_s"] = time.perf_counter() - t
-        true = np.concatenate([np.log2(1 + e.astype(np.float64)) for e in plain["events_arr"]])
-        allf = np.concatenate(feats) if multi else feats
-        err = predictor.load_error(np.concatenate(preds) if multi else preds, true)
-        bsf, (bk, bsg) = best_single_feature(allf, true)
-        pred_info.update({"spearman": err["spearman"], "mean_abs_log2": err["mean_abs_log2"],
-                          "best_single_feature": {"index": int(bk), "sign": int(bsg), "spearman": bsf}})
-        log(f"[bench] predictor: spearman {err['spearman']:.3f} (best single feature {bsf:.3f}), "
-            f"mean |dlog2| {err['mean_abs_log2']:.3f}")
+        if plain:
+            true = np.concatenate([np.log2(1 + e.astype(np.float64)) for e in plain["events_arr"]])
+            allf = np.concatenate(feats) if multi else feats
+            err = predictor.load_error(np.concatenate(preds) if multi else preds, true)
+            bsf, (bk, bsg) = best_single_feature(allf, true)
+            pred_info.update({"spearman": err["spearman"], "mean_abs_log2": err["mean_abs_log2"],
+                              "best_single_feature": {"index": int(bk), "sign": int(bsg), "spearman": bsf}})
+            log(f"[bench] predictor: spearman {err['spearman']:.3f} (best single feature {bsf:.3f}), "
+                f"mean |dlog2| {err['mean_abs_log2']:.3f}")
 
     # Autotuned two-dimensional schedule (bounded: a wall budget, and for long
     # lists a seeded sample of the faults).
     tuner = autotune.Autotuner(progress=log, budget_s=TUNE_BUDGET_S)
     t = time.perf_counter()
-    if args.no_tune:
+    if args.params:
+        params = dict(autotune.DEFAULT, **json.loads(args.params))
+    elif args.no_tune:
         params = dict(autotune.DEFAULT)
     elif multi:
         params = tuner.tune_batch([w.design for w in ws], job.ds, job.gs, [w.faults for w in ws], preds)
@@ -425,23 +440,30 @@ def main():
     # The ablation ladder: static order all light; a static heuristic (the
     # site's cone size) under the same heavy rule as the network; the network.
     ladder = {}
+    static = None
     if multi:
         allp = None if preds is None else np.concatenate(preds)
-        static = job.run_batch(psteps, 1, autotune.batch_kwargs(dict(params, heavy_quantile=None)), None)
+        if not args.only_headline:
+            static = job.run_batch(psteps, 1, autotune.batch_kwargs(dict(params, heavy_quantile=None)), None)
         best = job.run_batch(args.steps, args.warmup, autotune.batch_kwargs(params, allp), preds)
     else:
-        job.set_priority(None)
-        static = job.run(riros.MODE_TWO_D, psteps, 1, autotune.single_kwargs(dict(params, heavy_quantile=None)))
-        if feats is not None:
-            cone = np.ascontiguousarray(feats[:, 0], np.float32)
-            job.set_priority(cone)
-            heur = job.run(riros.MODE_TWO_D, psteps, 1, autotune.single_kwargs(params, cone))
-            ladder["static_cone_heuristic"] = {"fault_cycles_per_s": rate(heur), "kernel_ms": heur["kernel_ms"],
-                                               "identical": bool(same_results(heur, plain))}
+        if not args.only_headline:
+            job.set_priority(None)
+            static = job.run(riros.MODE_TWO_D, psteps, 1,
+                             autotune.single_kwargs(dict(params, heavy_quantile=None)))
+            if feats is not None:
+                cone = np.ascontiguousarray(feats[:, 0], np.float32)
+                job.set_priority(cone)
+                heur = job.run(riros.MODE_TWO_D, psteps, 1, autotune.single_kwargs(params, cone))
+                ladder["static_cone_heuristic"] = {"fault_cycles_per_s": rate(heur),
+                                                   "kernel_ms": heur["kernel_ms"],
+                                                   "identical": bool(same_results(heur, plain))}
         job.set_priority(preds)
         best = job.run(riros.MODE_TWO_D, args.steps, args.warmup, autotune.single_kwargs(params, preds))
-    log(f"[bench] two_d static: kernel {static['kernel_ms']:.3f} ms; with predictor: {best['kernel_ms']:.3f} ms")
-    same = same_results(plain, best) and same_results(static, best)
+    if static:
+        log(f"[bench] two_d static: kernel {static['kernel_ms']:.3f} ms")
+    log(f"[bench] two_d with predictor: kernel {best['kernel_ms']:.3f} ms")
+    same = (plain is None or same_results(plain, best)) and (static is None or same_results(static, best))
 
     # The paper keeps every fault for every cycle (no dropping): one extra run
     # in that convention on a seeded sample of the fault list, reported as
@@ -486,8 +508,9 @@ def main():
     ops_alg = OPS_PER_EVENT * E + OPS_PER_FC * FC
     ops_rate = ops_alg / (best["kernel_ms"] * 1e-3)
     total_faults = sum(w.faults.size for w in ws)
-    ladder = {"plain": {"fault_cycles_per_s": rate(plain), "kernel_ms": plain["kernel_ms"]},
-              "two_d_static_all_light": {"fault_cycles_per_s": rate(static), "kernel_ms": static["kernel_ms"]},
+    ladder = {"plain": None if plain is None else {"fault_cycles_per_s": rate(plain), "kernel_ms": plain["kernel_ms"]},
+              "two_d_static_all_light": None if static is None else
+              {"fault_cycles_per_s": rate(static), "kernel_ms": static["kernel_ms"]},
               **ladder,
               "two_d_predictor": {"fault_cycles_per_s": value, "kernel_ms": best["kernel_ms"]}}
     out = {
@@ -509,7 +532,7 @@ def main():
         "ablation": ladder,
         "plain": ladder["plain"],
         "two_d_predictor": ladder["two_d_predictor"],
-        "speedup_vs_plain": value / rate(plain),
+        "speedup_vs_plain": None if plain is None else value / rate(plain),
         "autotuned": {"params": params, "tune_s": tune_s, "budget_s": TUNE_BUDGET_S,
                       "sample_faults": min(total_faults, TUNE_SAMPLE) if not multi else total_faults},
         "predictor": pred_info,
