@@ -11,8 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_traffic_counters_are_used_only_for_their_sources():
-    got = bench.measured_traffic("medium")
-    text = open(os.path.join(ROOT, "profiles", "traffic_medium.md")).read()
+    got = bench.measured_traffic("large")
+    text = open(os.path.join(ROOT, "profiles", "traffic_large.md")).read()
     if f"`{bench.kernel_source_digest()}`" in text:
         assert got is not None and got > 0
         assert f"`{int(got)}`" in text
@@ -22,7 +22,7 @@ def test_traffic_counters_are_used_only_for_their_sources():
 
 def test_traffic_is_null_for_other_sources(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0000000000000000")
-    assert bench.measured_traffic("medium") is None
+    assert bench.measured_traffic("large") is None
     assert bench.measured_traffic("no_such_workload") is None
 
 
