@@ -320,6 +320,33 @@ int riros_last_kernel_ms(float* ms);
 const char* riros_last_error(void);
 
 /* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory: code under HIP graph       */
+/* capture, tight serving loops, harnesses that forbid hipMalloc.             */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the library's static scratch array, one per GPU it runs on, held
+ * until the process ends. */
+#define RIROS_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* riros_fault_sim in RIROS_MODE_PLAIN with device-resident inputs and outputs
+ * (opts->io_on_device must be 1; opts->words may be NULL), calling no
+ * hipMalloc, hipFree or allocating library routine: its workspace (each
+ * wavefront's faulty-value slots and register ping-pong, 16 * num_nodes +
+ * 16 * registers bytes) comes from the static scratch array, and the grid is
+ * cut to the wavefronts whose workspace fits it.  A design whose one-wavefront
+ * workspace exceeds RIROS_NOALLOC_SCRATCH_BYTES is rejected (RIROS_EINVAL,
+ * with the sizes in the message), and so are other modes and host I/O.  Faults
+ * are validated on the device; the call waits once for that check, then runs
+ * asynchronously on opts->stream (riros_last_kernel_ms does not time it).
+ * Every call on a GPU shares that GPU's array and keeps nothing in it between
+ * calls (the slots it uses are cleared by a kernel first): calls that overlap
+ * on one GPU race, so issue them on one stream.  Results equal riros_fault_sim's
+ * in plain mode. */
+int riros_fault_sim_noalloc(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
+                            const riros_sim_opts* opts, uint32_t* detect, uint64_t* events,
+                            riros_coverage* cov);
+
+/* ------------------------------------------------------------------------ */
 /* Peak-rate probes for the roofline (measurement tools, not part of the      */
 /* method): the rates a fault-simulation pass is compared against, measured   */
 /* on the current device.                                                     */

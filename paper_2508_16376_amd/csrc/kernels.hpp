@@ -85,6 +85,9 @@ hipError_t launch_fault_plain(const DevDesign& d, const GoldenView& g,
 hipError_t launch_validate_faults(const DevDesign& d, const riros_fault* faults, uint32_t F,
                                   uint32_t* bad_count, hipStream_t s);
 
+// Fill n 32-bit words with v (a kernel, so that it can be captured).
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
 hipError_t launch_coverage(const uint32_t* detect, const uint64_t* events, const uint64_t* words, uint32_t F,
                            uint32_t T, riros_coverage* cov, hipStream_t s);
 

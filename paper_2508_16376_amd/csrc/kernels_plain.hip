@@ -1,5 +1,7 @@
 // Golden simulation, the plain fault-parallel kernel, fault validation and
 // coverage reduction.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "wave_fault.hpp"
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(64) void k_fault_plain(DevDesign d, const uint64_t*
         if (threadIdx.x == 0) {
             detect_out[fi] = det;
             if (events_out) events_out[fi] = ev;
-            words_out[fi] = wk;
+            if (words_out) words_out[fi] = wk;
         }
     }
 }
@@ -217,7 +219,7 @@ __global__ void k_coverage(const uint32_t* __restrict__ detect, const uint64_t* 
         det += dc != RIROS_UNDETECTED;
         fc += dc != RIROS_UNDETECTED ? (uint64_t)dc + 1 : (uint64_t)T;
         if (events) ev += events[i];
-        wk += words[i];
+        if (words) wk += words[i];
     }
     det = wave_sum_u64(det);
     fc = wave_sum_u64(fc);
@@ -230,6 +232,19 @@ __global__ void k_coverage(const uint32_t* __restrict__ detect, const uint64_t* 
         atomicAdd((unsigned long long*)&cov->words, (unsigned long long)wk);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)&cov->total, (unsigned long long)F);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
 }
 
 __global__ void k_zero_cov(riros_coverage* cov)

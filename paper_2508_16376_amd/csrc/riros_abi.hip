@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -930,6 +931,113 @@ void riros_batch_free(riros_batch b)
     (void)hipDeviceSynchronize();
     free_batch(b);
     delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free plain fault simulation.  Its per-call workspace (each
+// wavefront's faulty-value slots and register ping-pong) lives in `scratch`,
+// a static device array of RIROS_NOALLOC_SCRATCH_BYTES that every GPU the
+// library runs on holds until the process ends.  In host code `scratch` is a
+// stand-in, not a device address: the array's address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever handed to a kernel.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[RIROS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on `dev` (which must be current).
+int scratch_on(int dev, unsigned char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return set_err(RIROS_EDEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_err(e == hipSuccess ? hipErrorInvalidSymbol : e, "scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (unsigned char*)g_scratch_ptr[dev];
+    return RIROS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int riros_fault_sim_noalloc(riros_design d, riros_golden g, const riros_fault* faults, uint32_t F,
+                            const riros_sim_opts* opts, uint32_t* detect, uint64_t* events, riros_coverage* cov)
+{
+    if (!d || !g || !opts) return set_err(RIROS_EINVAL, "NULL argument");
+    if (g->d != d) return set_err(RIROS_EINVAL, "golden trace belongs to another design");
+    if (opts->mode != RIROS_MODE_PLAIN) return set_err(RIROS_EINVAL, "riros_fault_sim_noalloc runs RIROS_MODE_PLAIN only");
+    if (!opts->io_on_device)
+        return set_err(RIROS_EINVAL, "riros_fault_sim_noalloc takes device-resident inputs and outputs (io_on_device = 1)");
+    if (F > 0 && (!faults || !detect)) return set_err(RIROS_EINVAL, "faults or detect is NULL");
+    if (opts->waves_per_cu < 0) return set_err(RIROS_EINVAL, "waves_per_cu < 0");
+    const riros::Image& im = d->img;
+    // One wavefront's workspace: N slots and 2R register words.
+    const size_t slot_bytes = (size_t)im.N * sizeof(riros::Slot);
+    const size_t reg_bytes = (size_t)2 * std::max(im.R, 1u) * sizeof(uint64_t);
+    const size_t per_wave = slot_bytes + reg_bytes;
+    if (per_wave > RIROS_NOALLOC_SCRATCH_BYTES) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "design needs %zu bytes of workspace per wavefront; the no-allocation scratch holds %zu",
+                      per_wave, (size_t)RIROS_NOALLOC_SCRATCH_BYTES);
+        return set_err(RIROS_EINVAL, buf);
+    }
+    if (riros::plain_lds_bytes(d->dev, riros::kWordsNarrow) > 160 * 1024)
+        return set_err(RIROS_EINVAL, "design too large for the plain kernel's LDS bitmap");
+    DeviceGuard guard(d->device);
+    hipStream_t s = (hipStream_t)opts->stream;
+    const uint32_t T = g->T;
+    unsigned char* base = nullptr;
+    int rc = scratch_on(d->device, &base);
+    if (rc) return rc;
+    if (F == 0) {
+        if (cov) HIP_TRY(riros::launch_coverage(nullptr, nullptr, nullptr, 0, T, cov, s), "coverage");
+        return RIROS_OK;
+    }
+    // Faults: validated on the device (the count of bad ones comes back to
+    // the host once); the counter is cleared by a kernel.
+    HIP_TRY(riros::launch_fill_u32(d->d_bad, 1, 0u, s), "validate clear");
+    HIP_TRY(riros::launch_validate_faults(d->dev, faults, F, d->d_bad, s), "validate launch");
+    uint32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, d->d_bad, sizeof bad, hipMemcpyDeviceToHost, s), "validate read");
+    HIP_TRY(hipStreamSynchronize(s), "validate sync");
+    if (bad) return set_err(RIROS_EINVAL, std::to_string(bad) + " invalid faults in device fault list");
+    // Grid: as riros_fault_sim's plain mode, cut to the wavefronts whose
+    // workspace fits the scratch array.
+    int wpc = opts->waves_per_cu > 0 ? opts->waves_per_cu : 16;
+    const uint32_t wpp = riros::words_per_pass(im.N, im.L, im.R, (uint32_t)std::min(wpc, 12));
+    const size_t lds = riros::plain_lds_bytes(d->dev, wpp);
+    const int lds_limit = (int)std::max<size_t>(1, (160 * 1024) / lds);
+    wpc = std::min(std::min(wpc, lds_limit), 32);
+    const uint64_t fit = (uint64_t)(RIROS_NOALLOC_SCRATCH_BYTES - 256) / per_wave;
+    const uint32_t blocks =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(F, (uint64_t)d->num_cu * wpc), fit));
+    riros::Slot* slots = (riros::Slot*)base;
+    const size_t reg_off = ((size_t)blocks * slot_bytes + 255) & ~(size_t)255;
+    uint64_t* regs = (uint64_t*)(base + reg_off);
+    // Slots left by an earlier call (of any design) must not carry a valid
+    // stamp: clear the ones this call uses.
+    HIP_TRY(riros::launch_fill_u32((uint32_t*)slots, (size_t)blocks * slot_bytes / 4, 0u, s), "scratch clear");
+    const uint64_t per_block = ((uint64_t)F + blocks - 1) / blocks;
+    riros::PlainWorkspace ws{slots, regs, d->stamp_dev};
+    HIP_TRY(riros::launch_fault_plain(d->dev, g->view(), faults, F, opts->drop ? 1 : 0, blocks, ws, wpp, detect,
+                                      events, opts->words, s),
+            "plain fault kernel");
+    HIP_TRY(riros::launch_advance_stamp(d->stamp_dev, per_block * T + 1, s), "stamp advance");
+    if (cov) HIP_TRY(riros::launch_coverage(detect, events, opts->words, F, T, cov, s), "coverage");
+    return RIROS_OK;
 }
 
 }  // extern "C"

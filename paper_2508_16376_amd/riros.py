@@ -31,7 +31,7 @@ EXPORTED = ["riros_load_design", "riros_free_design", "riros_golden_sim", "riros
             "riros_golden_read", "riros_fault_sim", "riros_design_info", "riros_last_kernel_ms",
             "riros_last_error", "riros_features", "riros_mlp_train", "riros_mlp_predict", "riros_mlp_grad",
             "riros_batch_create", "riros_batch_launch", "riros_batch_read", "riros_batch_free",
-            "riros_peak_hbm", "riros_peak_valu", "riros_golden_sim_many"]
+            "riros_peak_hbm", "riros_peak_valu", "riros_golden_sim_many", "riros_fault_sim_noalloc"]
 N_FEATURES = 6
 MLP_PARAMS = 4673
 MLP_WEIGHTS = MLP_PARAMS + 12
@@ -116,6 +116,8 @@ def lib():
         L.riros_golden_read.restype = I
         L.riros_fault_sim.argtypes = [P, P, P, U, ctypes.POINTER(SimOpts), P, P, ctypes.POINTER(Coverage)]
         L.riros_fault_sim.restype = I
+        L.riros_fault_sim_noalloc.argtypes = [P, P, P, U, ctypes.POINTER(SimOpts), P, P, ctypes.POINTER(Coverage)]
+        L.riros_fault_sim_noalloc.restype = I
         L.riros_design_info.argtypes = [P, ctypes.POINTER(U), ctypes.POINTER(U), ctypes.POINTER(U)]
         L.riros_design_info.restype = I
         L.riros_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
@@ -286,6 +288,16 @@ def fault_sim_device(design: Design, golden: Golden, faults_dev, F: int, detect_
                                  _ptr(detect_dev), _ptr(events_dev),
                                  ctypes.cast(_ptr(cov_dev), ctypes.POINTER(Coverage)) if cov_dev is not None
                                  else None))
+
+
+def fault_sim_noalloc(design: Design, golden: Golden, faults_dev, F: int, detect_dev, events_dev, cov_dev,
+                      opts: SimOpts):
+    """riros_fault_sim_noalloc: plain mode, device-resident buffers, no device
+    allocation (asynchronous on opts.stream after the fault check)."""
+    _check(lib().riros_fault_sim_noalloc(design.handle, golden.handle, _ptr(faults_dev), F, ctypes.byref(opts),
+                                         _ptr(detect_dev), _ptr(events_dev),
+                                         ctypes.cast(_ptr(cov_dev), ctypes.POINTER(Coverage))
+                                         if cov_dev is not None else None))
 
 
 def last_kernel_ms() -> float:
