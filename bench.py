@@ -47,6 +47,7 @@ BYTES_PER_WORD = 4
 OPS_PER_EVENT = 10
 OPS_PER_FC = 3
 NO_DROP_SAMPLE = 2000
+TRAIN_EPOCHS = 30
 PLAIN_STEPS = 2          # the plain kernel is timed on at most this many steps
 TUNE_BUDGET_S = 45.0
 TUNE_SAMPLE = 250000     # faults the tuner times each candidate on (seeded draw)
@@ -145,11 +146,13 @@ def make_workload(name):
 
 
 def held_out_training_runs():
-    """Designs of the medium, heavy-tailed and campaign shapes with seeds other
-    than any benchmark workload; their plain-kernel event counts train the
-    predictor."""
+    """Designs of the medium, heavy-tailed (at 1,000, 5,000 and 10,000 cycles)
+    and campaign shapes with seeds other than any benchmark workload; their
+    plain-kernel event counts train the predictor."""
     ws = [W.medium(seed=7001, F=20000, T=1000), W.medium(seed=7002, F=20000, T=1000),
-          W.heavy_tailed(seed=7003, F=20000, T=1000, n_nodes=30000)]
+          W.heavy_tailed(seed=7003, F=20000, T=1000, n_nodes=30000),
+          W.heavy_tailed(seed=7005, F=30000, T=5000, n_nodes=30000),
+          W.heavy_tailed(seed=7006, F=30000, T=10000, n_nodes=40000)]
     ws += W.campaign(seed=7004, n=6, nodes=(1000, 20000), faults=(2000, 10000), cycles=(500, 2000))
     runs = []
     for w in ws:
@@ -288,7 +291,7 @@ def train_predictor():
     x, y = predictor.samples_from_runs(runs)
     data_s = time.perf_counter() - t
     t = time.perf_counter()
-    wts, losses = predictor.train(x, y, epochs=8, batch=4096)
+    wts, losses = predictor.train(x, y, epochs=TRAIN_EPOCHS, batch=4096)
     train_s = time.perf_counter() - t
     del runs
     return wts, {"train_samples": int(x.shape[0]), "train_data_s": data_s, "train_s": train_s,

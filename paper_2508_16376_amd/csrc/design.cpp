@@ -237,6 +237,7 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
         r.words = event_words(o.op, o.width);
         img.bp_off[i] = rows;
         rows += o.width;
+        img.max_width = std::max<uint32_t>(img.max_width, o.width);
     }
     img.bp_rows = rows;
     return RIROS_OK;

@@ -54,6 +54,7 @@ struct Image {
     std::vector<NodeRec> rec;                   // per internal node
     std::vector<uint32_t> bp_off;               // first bit-plane row of each node (prefix sum of widths)
     uint32_t bp_rows = 0;                       // total bit-plane rows (sum of widths)
+    uint32_t max_width = 0;                     // widest node
 };
 
 // Per-node graph features of the load predictor (internal numbering):

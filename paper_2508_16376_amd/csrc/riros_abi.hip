@@ -516,6 +516,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.unified = opts->unified;
         p.share = opts->struct_share;
         p.heavy_wg = opts->heavy_wg > 0 ? opts->heavy_wg : 64;
+        p.w32 = im.max_width <= 32;
         p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
@@ -732,7 +733,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
-    uint32_t Nmax = 0, Lmax = 0, Rmax = 0, Tmax = 0;
+    uint32_t Nmax = 0, Lmax = 0, Rmax = 0, Tmax = 0, Wmax = 0;
     for (uint32_t i = 0; i < n; ++i) {
         if (!designs[i] || !goldens[i] || goldens[i]->d != designs[i])
             return set_err(RIROS_EINVAL, "design " + std::to_string(i) + ": missing or mismatched golden trace");
@@ -749,6 +750,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         Lmax = std::max(Lmax, im.L);
         Rmax = std::max(Rmax, im.R);
         Tmax = std::max(Tmax, goldens[i]->T);
+        Wmax = std::max(Wmax, im.max_width);
     }
     if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
     const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax, riros::kWordsNarrow) * sizeof(uint32_t);
@@ -861,6 +863,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.unified = opts->unified;
     p.share = opts->struct_share;
     p.heavy_wg = opts->heavy_wg > 0 ? (uint32_t)opts->heavy_wg : 64u;
+    p.w32 = Wmax <= 32;
     p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);

@@ -21,6 +21,8 @@
 // appear.  Where a fault runs never changes its result.
 #include <hipcub/hipcub.hpp>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "twod.hpp"
 #include "wave_fault.hpp"
@@ -82,13 +84,14 @@ struct SortedIds {
     }
 };
 
-// (node id, faulty ^ golden) pairs.
-template <int C>
+// (node id, faulty ^ golden) pairs; V is the value word (uint32_t when no
+// node of the design is wider than 32 bits).
+template <int C, typename V = uint64_t>
 struct DeltaSet {
     uint32_t id[C];
-    uint64_t dx[C];
+    V dx[C];
     uint32_t n;
-    __device__ __forceinline__ bool add(uint32_t i, uint64_t x)
+    __device__ __forceinline__ bool add(uint32_t i, V x)
     {
         if (n >= (uint32_t)C) return false;
 #pragma unroll
@@ -100,9 +103,9 @@ struct DeltaSet {
         n++;
         return true;
     }
-    __device__ __forceinline__ uint64_t find(uint32_t i, bool& hit) const
+    __device__ __forceinline__ V find(uint32_t i, bool& hit) const
     {
-        uint64_t r = 0;
+        V r = 0;
 #pragma unroll
         for (int k = 0; k < C; ++k)
             if (((uint32_t)k < n) && id[k] == i) {
@@ -116,6 +119,58 @@ struct DeltaSet {
 __device__ __forceinline__ uint32_t pick4(uint32_t k, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+
+// A node's golden value in cycle t from the node-major trace: the whole word,
+// or (32-bit lanes, every node at most 32 bits wide) its low half, one
+// 4-byte load.
+template <typename V>
+__device__ __forceinline__ V gold_at(const uint64_t* __restrict__ Gn, size_t i)
+{
+    if constexpr (sizeof(V) == 8) return Gn[i];
+    else return reinterpret_cast<const uint32_t*>(Gn)[2 * i];
+}
+
+// The operator table on 32-bit words (every operand and result at most 32
+// bits wide): the same results as apply_opw on their zero-extended values.
+__device__ __forceinline__ uint32_t apply_opw32(uint32_t op, uint32_t width, uint32_t pb, uint32_t pc, uint32_t x0,
+                                                uint32_t x1, uint32_t x2)
+{
+    uint32_t r;
+    switch (op) {
+    case RIROS_OP_ADD: r = x0 + x1; break;
+    case RIROS_OP_SUB: r = x0 - x1; break;
+    case RIROS_OP_AND: r = x0 & x1; break;
+    case RIROS_OP_OR: r = x0 | x1; break;
+    case RIROS_OP_XOR: r = x0 ^ x1; break;
+    case RIROS_OP_NOT: r = ~x0; break;
+    case RIROS_OP_MUX: r = x0 != 0 ? x2 : x1; break;
+    case RIROS_OP_SHL: r = pb >= 32 ? 0u : (x0 << pb); break;
+    case RIROS_OP_SHR:
+    case RIROS_OP_SLICE: r = pb >= 32 ? 0u : (x0 >> pb); break;
+    case RIROS_OP_EQ: r = x0 == x1; break;
+    case RIROS_OP_NE: r = x0 != x1; break;
+    case RIROS_OP_ULT: r = x0 < x1; break;
+    case RIROS_OP_CONCAT: r = (pc >= 32 ? 0u : (x0 << pc)) | x1; break;
+    case RIROS_OP_MUL: r = x0 * x1; break;
+    default: r = 0; break;
+    }
+    return width >= 32 ? r : (r & ((1u << width) - 1u));
+}
+
+template <typename V>
+__device__ __forceinline__ V apply_op_v(uint32_t op, uint32_t width, uint32_t pb, uint32_t pc, V x0, V x1, V x2)
+{
+    if constexpr (sizeof(V) == 8) return apply_opw(op, width, pb, pc, x0, x1, x2);
+    else return apply_opw32(op, width, pb, pc, x0, x1, x2);
+}
+
+template <typename V>
+__device__ __forceinline__ V apply_fault_v(V v, uint32_t bit, uint32_t stuck, uint32_t t, uint32_t t0)
+{
+    const V m = (V)1 << bit;
+    if (stuck == RIROS_FAULT_FLIP) return t == t0 ? (v ^ m) : v;
+    return stuck ? (v | m) : (v & ~m);
 }
 
 // Per-lane view of a fault's design: everything the light path reads.
@@ -159,8 +214,10 @@ __device__ __forceinline__ uint64_t site_words(int drop, uint32_t det, uint32_t 
 // load of its bit-plane; only the site can diverge in such a cycle, with
 // faulty = golden ^ (1 << bit).  Otherwise the lane evaluates its pending
 // nodes in increasing id order (a topological order) from the node-major
-// golden values of the operands xor their divergence deltas.
-template <int C, bool BATCH>
+// golden values of the operands xor their divergence deltas.  V: the value
+// word, uint32_t when no node of the design(s) is wider than 32 bits (half
+// the registers and vector instructions per value), else uint64_t.
+template <int C, bool BATCH, typename V>
 __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict__ faults,
                             uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
@@ -187,8 +244,8 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     uint32_t sf0 = 0, sf1 = 0, sf2 = 0, sf3 = 0;
     bool exhausted = nlight == 0;
     SortedIds<C> pend;
-    DeltaSet<C> div;
-    DeltaSet<CR> rcur, rnxt;
+    DeltaSet<C, V> div;
+    DeltaSet<CR, V> rcur, rnxt;
     pend.n = div.n = rcur.n = rnxt.n = 0;
 
     bool finished = false;   // this lane finished or handed over a fault in the last iteration
@@ -255,7 +312,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         bool esc_now = false;
         // Record a divergent node: keep its delta, schedule its users, stage
         // register next states, note output mismatches.
-        auto on_divergent = [&](uint32_t n, uint64_t delta, const NodeRec& r, uint32_t p0, uint32_t p1,
+        auto on_divergent = [&](uint32_t n, V delta, const NodeRec& r, uint32_t p0, uint32_t p1,
                                 uint32_t p2, uint32_t p3) {
             if (!div.add(n, delta)) { esc_now = true; return; }
             if ((r.flags & DF_PO) && det == RIROS_UNDETECTED) det = t;
@@ -307,7 +364,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 }
                 ev++;
                 wk += srec.words;
-                on_divergent(site, 1ull << fbit, srec, sf0, sf1, sf2, sf3);
+                on_divergent(site, (V)1 << fbit, srec, sf0, sf1, sf2, sf3);
                 evaluated = true;
             } else {
                 // Divergent registers are evaluated first, straight from
@@ -339,15 +396,16 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             }
             const NodeRec r = d.rec[n];
             const uint32_t T = d.T;
-            const uint64_t gv = d.Gn[(size_t)n * T + t];
+            const V gv = gold_at<V>(d.Gn, (size_t)n * T + t);
             const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
             const int ar = comb ? dev_arity(r.op) : 0;
             const uint32_t i0 = ar > 0 ? r.a : n;
             const uint32_t i1 = ar > 1 ? r.b : i0;
             const uint32_t i2 = ar > 2 ? r.c : i0;
-            uint64_t x0 = d.Gn[(size_t)i0 * T + t], x1 = d.Gn[(size_t)i1 * T + t], x2 = d.Gn[(size_t)i2 * T + t];
+            V x0 = gold_at<V>(d.Gn, (size_t)i0 * T + t), x1 = gold_at<V>(d.Gn, (size_t)i1 * T + t),
+              x2 = gold_at<V>(d.Gn, (size_t)i2 * T + t);
             const uint32_t p0 = d.fo[r.fo0], p1 = d.fo[r.fo0 + 1], p2 = d.fo[r.fo0 + 2], p3 = d.fo[r.fo0 + 3];
-            uint64_t delta = 0;
+            V delta = 0;
             bool din = false;
             if (r.op == RIROS_OP_REG) {
                 delta = rcur.find(n, din);
@@ -355,9 +413,9 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 x0 ^= div.find(i0, din);
                 if (ar > 1) x1 ^= div.find(i1, din);
                 if (ar > 2) x2 ^= div.find(i2, din);
-                delta = apply_opw(r.op, r.width, r.b, r.c, x0, x1, x2) ^ gv;
+                delta = apply_op_v<V>(r.op, r.width, r.b, r.c, x0, x1, x2) ^ gv;
             }
-            if (n == site) delta = apply_fault(gv ^ delta, fbit, fval, t, ft0) ^ gv;
+            if (n == site) delta = apply_fault_v<V>(gv ^ delta, fbit, fval, t, ft0) ^ gv;
             const bool dout = delta != 0;
             if (din || dout) {
                 ev++;
@@ -522,8 +580,9 @@ struct MaxShape {
 constexpr uint32_t kMaxShare = 4;
 
 // Capacities up to 8 are held to three wavefronts per SIMD (at most 168
-// registers per lane; checked free of spills).
-template <int C, bool BATCH, bool STRUCT>
+// registers per lane; checked free of spills).  W32: every node of the
+// launch's designs is at most 32 bits wide, so light lanes keep 32-bit values.
+template <int C, bool BATCH, bool STRUCT, bool W32>
 __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu_waves_per_eu(C <= 8 ? 3 : 1)))
 void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
@@ -568,15 +627,17 @@ void k_twod_a(
         const uint32_t nlight = F - nh;
         const uint32_t waves = gridDim.x * (blockDim.x >> 6);
         const uint32_t lanes = min(64u, max(1u, (nlight + waves - 1) / waves));
-        light_phase<C, BATCH>(src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out,
-                              events_out, words_out, lanes, rate_num);
+        light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(
+            src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out, events_out, words_out, lanes,
+            rate_num);
         if (unified && wave == 0)
             drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
                                   events_out, words_out);
     } else {
         const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
-        light_phase<C, BATCH>(src, faults, F, order, ctr, esc, drop, detect_out, events_out, words_out, lanes,
-                              rate_num);
+        light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(src, faults, F, order, ctr, esc, drop,
+                                                                          detect_out, events_out, words_out, lanes,
+                                                                          rate_num);
     }
 }
 
@@ -771,16 +832,24 @@ static uint32_t resident_blocks(const void* kern, size_t lds, uint32_t want, uin
     return std::max(1u, std::min<uint32_t>(std::min(want, kTicketPad), (uint32_t)per_cu * (uint32_t)cus));
 }
 
-template <int C, bool BATCH>
+template <int C, bool BATCH, bool W32>
 static const void* kernel_a(bool structural)
 {
-    return structural ? (const void*)k_twod_a<C, BATCH, true> : (const void*)k_twod_a<C, BATCH, false>;
+    return structural ? (const void*)k_twod_a<C, BATCH, true, W32> : (const void*)k_twod_a<C, BATCH, false, W32>;
 }
 
-static const void* kernel_a_any(int cap, bool batch, bool structural)
+// 32-bit light lanes exist for capacities 4 and 8 (capacity 16 keeps 64-bit
+// values).
+static const void* kernel_a_any(int cap, bool batch, bool structural, bool w32)
 {
-    if (batch) return cap == 4 ? kernel_a<4, true>(structural) : (cap == 16 ? kernel_a<16, true>(structural) : kernel_a<8, true>(structural));
-    return cap == 4 ? kernel_a<4, false>(structural) : (cap == 16 ? kernel_a<16, false>(structural) : kernel_a<8, false>(structural));
+    if (batch) {
+        if (cap == 16) return kernel_a<16, true, false>(structural);
+        if (cap == 4) return w32 ? kernel_a<4, true, true>(structural) : kernel_a<4, true, false>(structural);
+        return w32 ? kernel_a<8, true, true>(structural) : kernel_a<8, true, false>(structural);
+    }
+    if (cap == 16) return kernel_a<16, false, false>(structural);
+    if (cap == 4) return w32 ? kernel_a<4, false, true>(structural) : kernel_a<4, false, false>(structural);
+    return w32 ? kernel_a<8, false, true>(structural) : kernel_a<8, false, false>(structural);
 }
 
 // Launch A's grid for `want` wavefronts: workgroups of 64 * share threads
@@ -790,10 +859,11 @@ struct GridA {
     uint32_t blocks = 1, threads = 64;
 };
 
-static GridA twod_grid_a(int cap, bool batch, bool structural, const MaxShape& mx, uint32_t want, int share)
+static GridA twod_grid_a(int cap, bool batch, bool structural, bool w32, const MaxShape& mx, uint32_t want,
+                         int share)
 {
     GridA g;
-    const void* k = kernel_a_any(cap, batch, structural);
+    const void* k = kernel_a_any(cap, batch, structural, w32);
     if (!structural) {
         g.blocks = resident_blocks(k, 0, want);
         return g;
@@ -840,7 +910,7 @@ static void launch_b(uint32_t wg, uint32_t blocks, size_t lds, hipStream_t s, co
                            ws, span, detect, events, words);
 }
 
-template <int C, bool BATCH>
+template <int C, bool BATCH, bool W32>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
                                 const uint32_t* order, bool heavy, int unified, int share, uint32_t heavy_wg,
                                 TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
@@ -852,14 +922,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
                                        (int)ldsb);
     if (e != hipSuccess) return e;
     const bool structural = heavy || unified;
-    const GridA ga = twod_grid_a(C, BATCH, structural, mx, blocks, share);
+    const GridA ga = twod_grid_a(C, BATCH, structural, W32, mx, blocks, share);
     if (unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
-        hipLaunchKernelGGL((k_twod_a<C, BATCH, true>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, true, W32>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
                            order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, detect, events, words);
     } else {
-        hipLaunchKernelGGL((k_twod_a<C, BATCH, false>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
+        hipLaunchKernelGGL((k_twod_a<C, BATCH, false, W32>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
                            ctr, esc, drop, ws, rate_num, 0, 0, detect, events, words);
     }
     const uint32_t wgb = heavy_wg > 64 ? heavy_wg : 64u;
@@ -871,17 +941,21 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 }
 
 template <bool BATCH>
-static hipError_t launch_twod_any(int cap, const DesignSrc& src, const MaxShape& mx, const riros_fault* faults,
-                                  uint32_t F, const uint32_t* order, bool heavy, int unified, int share,
-                                  uint32_t heavy_wg, TwoDCounters* ctr, uint32_t* esc, int drop,
+static hipError_t launch_twod_any(int cap, bool w32, const DesignSrc& src, const MaxShape& mx,
+                                  const riros_fault* faults, uint32_t F, const uint32_t* order, bool heavy, int unified,
+                                  int share, uint32_t heavy_wg, TwoDCounters* ctr, uint32_t* esc, int drop,
                                   const PlainWorkspace& ws, uint64_t span, uint32_t blocks, uint32_t rate_num,
                                   uint32_t* detect, uint64_t* events, uint64_t* words, hipStream_t s)
 {
+#define RIROS_TWOD_C(CAP, W)                                                                                       \
+    launch_twod_c<CAP, BATCH, W>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, \
+                                 blocks, rate_num, detect, events, words, s)
     switch (cap) {
-    case 4: return launch_twod_c<4, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
-    case 16: return launch_twod_c<16, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
-    default: return launch_twod_c<8, BATCH>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, blocks, rate_num, detect, events, words, s);
+    case 4: return w32 ? RIROS_TWOD_C(4, true) : RIROS_TWOD_C(4, false);
+    case 16: return RIROS_TWOD_C(16, false);
+    default: return w32 ? RIROS_TWOD_C(8, true) : RIROS_TWOD_C(8, false);
     }
+#undef RIROS_TWOD_C
 }
 
 // Ordering by priority (descending) and the heavy prefix count; outside any
@@ -951,7 +1025,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const MaxShape mx{d.N, d.L, d.R, words_per_pass(d.N, d.L, d.R, (uint32_t)std::max(1, p.waves_per_cu))};
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
-    hipError_t e = launch_twod_any<false>(p.light_cap, src, mx, faults, F, order, heavy, p.unified, p.share,
+    hipError_t e = launch_twod_any<false>(p.light_cap, p.w32, src, mx, faults, F, order, heavy, p.unified, p.share,
                                           (uint32_t)p.heavy_wg, ctr, esc, drop, heavy_ws, span, blocks, rate_num,
                                           detect, events, words, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
@@ -966,13 +1040,16 @@ hipError_t prepare_twod_batch(BatchPlan& b)
     auto attr = [&](const void* f, size_t lds) {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    attr((const void*)k_twod_a<4, true, true>, lds_bytes_a(mx));
-    attr((const void*)k_twod_a<8, true, true>, lds_bytes_a(mx));
-    attr((const void*)k_twod_a<16, true, true>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<4, true, true, false>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<8, true, true, false>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<16, true, true, false>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<4, true, true, true>, lds_bytes_a(mx));
+    attr((const void*)k_twod_a<8, true, true, true>, lds_bytes_a(mx));
     attr((const void*)k_twod_b<true, false>, lds_bytes_b(mx));
     attr((const void*)k_twod_b<true, true>, lds_bytes_b(mx));
     if (e == hipSuccess) {
-        const GridA ga = twod_grid_a(b.light_cap, true, b.heavy || b.unified, mx, b.blocks, b.share);
+        const GridA ga = twod_grid_a(b.light_cap, true, b.heavy || b.unified, b.w32 && b.light_cap != 16, mx, b.blocks,
+                                     b.share);
         b.blocks_a = ga.blocks;
         b.threads_a = ga.threads;
         const uint32_t wgb = b.heavy_wg > 64 ? b.heavy_wg : 64u;
@@ -1009,8 +1086,8 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     DesignSrc src{b.td_host0, b.tg_host0, b.td, b.tg, b.did};
     const MaxShape mx{b.Nmax, b.Lmax, b.Rmax, b.wpp};
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
-#define RIROS_LAUNCH_A(CAP, HV, L)                                                                           \
-    hipLaunchKernelGGL((k_twod_a<CAP, true, HV>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,     \
+#define RIROS_LAUNCH_A(CAP, HV, L, W)                                                                        \
+    hipLaunchKernelGGL((k_twod_a<CAP, true, HV, W>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,  \
                        b.faults, b.F, b.order,                                                                   \
                        ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0, b.detect, b.events,   \
                        b.words)
@@ -1019,15 +1096,15 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
                            kNone);
     if (b.heavy || b.unified) {
         switch (b.light_cap) {
-        case 4: RIROS_LAUNCH_A(4, true, lds); break;
-        case 16: RIROS_LAUNCH_A(16, true, lds); break;
-        default: RIROS_LAUNCH_A(8, true, lds); break;
+        case 4: if (b.w32) RIROS_LAUNCH_A(4, true, lds, true); else RIROS_LAUNCH_A(4, true, lds, false); break;
+        case 16: RIROS_LAUNCH_A(16, true, lds, false); break;
+        default: if (b.w32) RIROS_LAUNCH_A(8, true, lds, true); else RIROS_LAUNCH_A(8, true, lds, false); break;
         }
     } else {
         switch (b.light_cap) {
-        case 4: RIROS_LAUNCH_A(4, false, 0); break;
-        case 16: RIROS_LAUNCH_A(16, false, 0); break;
-        default: RIROS_LAUNCH_A(8, false, 0); break;
+        case 4: if (b.w32) RIROS_LAUNCH_A(4, false, 0, true); else RIROS_LAUNCH_A(4, false, 0, false); break;
+        case 16: RIROS_LAUNCH_A(16, false, 0, false); break;
+        default: if (b.w32) RIROS_LAUNCH_A(8, false, 0, true); else RIROS_LAUNCH_A(8, false, 0, false); break;
         }
     }
 #undef RIROS_LAUNCH_A

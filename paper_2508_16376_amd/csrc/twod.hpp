@@ -24,6 +24,7 @@ struct TwoDParams {
     int unified = 0;            // waves out of light work take handed-over faults during launch A
     int share = 0;              // launch A wavefronts per structural workspace (0 = as the LDS needs)
     int heavy_wg = 64;          // threads that simulate one structural fault (64, 128 or 256)
+    bool w32 = false;           // every node at most 32 bits wide: light lanes keep 32-bit values
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -63,6 +64,7 @@ struct BatchPlan {
     int unified = 0;          // phase 3 in launch A (see riros_sim_opts.unified)
     int share = 0;            // launch A wavefronts per structural workspace (see riros_sim_opts.struct_share)
     uint32_t heavy_wg = 64;   // threads per structural fault (see riros_sim_opts.heavy_wg)
+    bool w32 = false;         // every node of every design at most 32 bits wide (32-bit light lanes)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;

@@ -120,3 +120,27 @@ def test_campaign_golden_in_graph_on_every_replay(small_campaign):
             np.testing.assert_array_equal(ev, refs[i][1], err_msg=f"replay {rep} design {i}")
         np.testing.assert_array_equal(gs[0].read(), oracle.golden(ws[0].design, ws[0].stimulus, ws[0].T))
     b.close()
+
+
+def test_campaign_of_narrow_template_designs():
+    """A campaign whose designs are all at most 32 bits wide (template designs:
+    light lanes keep 32-bit values) with priorities, a heavy prefix on
+    two-wavefront workgroups and the unified schedule, on two replays."""
+    ws = []
+    for k in range(4):
+        s = 626262 + 1000 * k
+        d = W.gen_templates(s, n_nodes=1500 + 700 * k, name=f"tmpl{k}")
+        T = 300 + 100 * k
+        ws.append(W.Workload(d.name, d, W.gen_stimulus(s, d, T), W.gen_faults(s, d, 1500), T))
+    refs = [oracle.fault_sim(w.design, w.stimulus, w.T, w.faults) for w in ws]
+    ds, gs = _load(ws)
+    prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
+    b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=float(np.quantile(np.concatenate(prios), 0.95)),
+                    monitor_rate=2.0, unified=1, struct_share=2, heavy_wg=128, light_cap=4)
+    for rep in range(2):
+        b.launch()
+        for i in range(len(ws)):
+            det, ev, _ = b.read(i)
+            np.testing.assert_array_equal(det, refs[i][0], err_msg=f"replay {rep} design {i}")
+            np.testing.assert_array_equal(ev, refs[i][1], err_msg=f"replay {rep} design {i}")
+    b.close()

@@ -156,3 +156,46 @@ def test_trained_network_beats_the_untrained_one_and_static_order(small):
           f"best single feature={best_feature:.3f}")
     assert trained > untrained + 0.1
     assert trained > abs(static) + 0.1
+
+
+def test_trained_network_beats_the_best_feature_and_schedules_faster():
+    """What the trained network gains over the method without it, on the large
+    workload (200,000 nodes, 10,000 cycles, 1,000,000 faults), trained as the
+    benchmark trains it on held-out designs: it ranks the faults' loads better
+    than the best single feature, and the two-dimensional pass it orders is
+    faster than the static list order and than ordering by the site's cone
+    size (a static heuristic) under the same schedule; results are identical."""
+    import bench
+    runs = bench.held_out_training_runs()
+    x, y = predictor.samples_from_runs(runs)
+    wts, _ = predictor.train(x, y, epochs=bench.TRAIN_EPOCHS, batch=4096)
+    del runs
+    w = W.large()
+    d = riros.Design(w.design)
+    g = riros.Golden(d, w.stimulus, w.T)
+    feats = riros.features(d, g, w.faults)
+    kw = dict(monitor_rate=8.0, light_cap=4, waves_per_cu=12)
+    base_det, base_ev, _ = riros.fault_sim(d, g, w.faults, mode=riros.MODE_TWO_D, **kw)
+    true_load = np.log2(1 + base_ev.astype(np.float64))
+    pred = riros.mlp_predict(wts, feats)
+    trained = predictor.load_error(pred, true_load)["spearman"]
+    best_feature = max(abs(predictor.load_error(feats[:, j], true_load)["spearman"]) for j in range(6))
+
+    def pass_ms(prio):
+        ms = []
+        for k in range(4):
+            det, ev, _ = riros.fault_sim(d, g, w.faults, mode=riros.MODE_TWO_D, priority=prio, **kw)
+            if k:
+                ms.append(riros.last_kernel_ms())
+        np.testing.assert_array_equal(det, base_det)
+        np.testing.assert_array_equal(ev, base_ev)
+        return float(np.mean(ms))
+
+    static_ms = pass_ms(None)
+    cone_ms = pass_ms(np.ascontiguousarray(feats[:, 0]))
+    net_ms = pass_ms(pred)
+    print(f"[predictor] large: spearman trained={trained:.3f} best single feature={best_feature:.3f}; "
+          f"pass static={static_ms:.1f} ms cone={cone_ms:.1f} ms network={net_ms:.1f} ms")
+    assert trained > best_feature + 0.02
+    assert net_ms < 0.9 * static_ms
+    assert net_ms < 0.95 * cone_ms
