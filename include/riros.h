@@ -198,6 +198,11 @@ typedef struct {
                               fault's frontier split across 2 or 4 wavefronts, one
                               barrier per pass: the paper spreads a high-load node
                               over many workers, Sec. IV-C); 0 = 64 */
+    int32_t lockstep;      /* TWO_D: 1 = a light lane about to start a cycle waits while
+                              another lane of its wavefront is still inside one, so the
+                              lanes of a wavefront (faults of one node or one template,
+                              when ordered by priority) walk their frontiers in step; 0 =
+                              every lane runs on.  Never changes a result */
 } riros_sim_opts;
 
 typedef struct {

@@ -39,10 +39,11 @@ SPACE = {
     "waves_per_cu": [8, 12, 16],
     "struct_share": [1, 2, 4],
     "heavy_wg": [64, 128, 256],
+    "lockstep": [0, 1],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
-           "heavy_wg": 64, "heavy_quantile": None}
+           "heavy_wg": 64, "lockstep": 0, "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -57,7 +58,7 @@ def _opts(p, priority):
         theta = float(np.quantile(priority, p["heavy_quantile"]))
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
             "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0),
-            "heavy_wg": p.get("heavy_wg", 0), "theta": theta}
+            "heavy_wg": p.get("heavy_wg", 0), "lockstep": p.get("lockstep", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):

@@ -517,6 +517,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.share = opts->struct_share;
         p.heavy_wg = opts->heavy_wg > 0 ? opts->heavy_wg : 64;
         p.w32 = im.max_width <= 32;
+        p.lockstep = opts->lockstep ? 1 : 0;
         p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
@@ -864,6 +865,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.share = opts->struct_share;
     p.heavy_wg = opts->heavy_wg > 0 ? (uint32_t)opts->heavy_wg : 64u;
     p.w32 = Wmax <= 32;
+    p.lockstep = opts->lockstep ? 1 : 0;
     p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);

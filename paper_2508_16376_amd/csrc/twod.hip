@@ -222,7 +222,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                             uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
                             uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out,
-                            uint32_t lanes, uint32_t rate_num)
+                            uint32_t lanes, uint32_t rate_num, int lockstep)
 {
     // Register next-state deltas: a pipeline keeps one per divergent stage.
     // Batched lanes hold their design's pointers in registers, so they keep
@@ -308,6 +308,13 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         }
         if (__ballot(fi != kNone) == 0) break;
         if (fi == kNone) continue;
+        // Lockstep (optional): a lane about to start a cycle waits while
+        // another lane of the wavefront is still inside one, so that the
+        // lanes start their cycles together and walk frontiers of the same
+        // shape (faults of one node, or of one template) in step: the same
+        // branches, and records and golden lines shared between lanes.
+        const uint64_t inside = __ballot(in_cycle);
+        if (lockstep && !in_cycle && inside != 0) continue;
 
         bool esc_now = false;
         // Record a divergent node: keep its delta, schedule its users, stage
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu
 void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
     const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-    uint32_t rate_num, int unified, int group_heavy, uint32_t* __restrict__ detect_out,
+    uint32_t rate_num, int unified, int group_heavy, int lockstep, uint32_t* __restrict__ detect_out,
     uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     if constexpr (STRUCT) {
@@ -629,7 +636,7 @@ void k_twod_a(
         const uint32_t lanes = min(64u, max(1u, (nlight + waves - 1) / waves));
         light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(
             src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out, events_out, words_out, lanes,
-            rate_num);
+            rate_num, lockstep);
         if (unified && wave == 0)
             drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
                                   events_out, words_out);
@@ -637,7 +644,7 @@ void k_twod_a(
         const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
         light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(src, faults, F, order, ctr, esc, drop,
                                                                           detect_out, events_out, words_out, lanes,
-                                                                          rate_num);
+                                                                          rate_num, lockstep);
     }
 }
 
@@ -913,8 +920,8 @@ static void launch_b(uint32_t wg, uint32_t blocks, size_t lds, hipStream_t s, co
 template <int C, bool BATCH, bool W32>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
                                 const uint32_t* order, bool heavy, int unified, int share, uint32_t heavy_wg,
-                                TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws, uint64_t span,
-                                uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
+                                int lockstep, TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws,
+                                uint64_t span, uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
                                 uint64_t* words, hipStream_t s)
 {
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
@@ -927,10 +934,11 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, true, W32>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
-                           order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, detect, events, words);
+                           order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, lockstep, detect, events,
+                           words);
     } else {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, false, W32>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
-                           ctr, esc, drop, ws, rate_num, 0, 0, detect, events, words);
+                           ctr, esc, drop, ws, rate_num, 0, 0, lockstep, detect, events, words);
     }
     const uint32_t wgb = heavy_wg > 64 ? heavy_wg : 64u;
     const uint32_t bb = resident_blocks(kernel_b<BATCH>(wgb), ldsb, blocks, wgb);
@@ -943,12 +951,13 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 template <bool BATCH>
 static hipError_t launch_twod_any(int cap, bool w32, const DesignSrc& src, const MaxShape& mx,
                                   const riros_fault* faults, uint32_t F, const uint32_t* order, bool heavy, int unified,
-                                  int share, uint32_t heavy_wg, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                  int share, uint32_t heavy_wg, int lockstep, TwoDCounters* ctr, uint32_t* esc, int drop,
                                   const PlainWorkspace& ws, uint64_t span, uint32_t blocks, uint32_t rate_num,
                                   uint32_t* detect, uint64_t* events, uint64_t* words, hipStream_t s)
 {
 #define RIROS_TWOD_C(CAP, W)                                                                                       \
-    launch_twod_c<CAP, BATCH, W>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, ctr, esc, drop, ws, span, \
+    launch_twod_c<CAP, BATCH, W>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, lockstep, ctr, esc, drop,   \
+                                 ws, span,                                                                            \
                                  blocks, rate_num, detect, events, words, s)
     switch (cap) {
     case 4: return w32 ? RIROS_TWOD_C(4, true) : RIROS_TWOD_C(4, false);
@@ -1026,7 +1035,8 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
     hipError_t e = launch_twod_any<false>(p.light_cap, p.w32, src, mx, faults, F, order, heavy, p.unified, p.share,
-                                          (uint32_t)p.heavy_wg, ctr, esc, drop, heavy_ws, span, blocks, rate_num,
+                                          (uint32_t)p.heavy_wg, p.lockstep, ctr, esc, drop, heavy_ws, span, blocks,
+                                          rate_num,
                                           detect, events, words, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
     if (hipEventRecord(ev1, s) != hipSuccess) { err = "event record"; return RIROS_EDEVICE; }
@@ -1089,7 +1099,8 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
 #define RIROS_LAUNCH_A(CAP, HV, L, W)                                                                        \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV, W>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,  \
                        b.faults, b.F, b.order,                                                                   \
-                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0, b.detect, b.events,   \
+                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0, b.lockstep, b.detect,  \
+                       b.events,                                                                                  \
                        b.words)
     if (b.unified)
         hipLaunchKernelGGL(k_fill_u32, dim3((b.F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, b.F + kTicketPad,

@@ -25,6 +25,7 @@ struct TwoDParams {
     int share = 0;              // launch A wavefronts per structural workspace (0 = as the LDS needs)
     int heavy_wg = 64;          // threads that simulate one structural fault (64, 128 or 256)
     bool w32 = false;           // every node at most 32 bits wide: light lanes keep 32-bit values
+    int lockstep = 0;           // light lanes of a wavefront start their cycles together
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -65,6 +66,7 @@ struct BatchPlan {
     int share = 0;            // launch A wavefronts per structural workspace (see riros_sim_opts.struct_share)
     uint32_t heavy_wg = 64;   // threads per structural fault (see riros_sim_opts.heavy_wg)
     bool w32 = false;         // every node of every design at most 32 bits wide (32-bit light lanes)
+    int lockstep = 0;         // light lanes of a wavefront start their cycles together
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;

@@ -288,6 +288,19 @@ def test_two_d_workgroup_split_medium_no_drop_sample():
            heavy_wg=256)
 
 
+@pytest.mark.parametrize("light_cap", [4, 8])
+def test_two_d_lockstep_lanes(small, tiny, light_cap):
+    """Light lanes that start their cycles together (lockstep), with and
+    without priorities (faults of one site adjacent), drop on and off."""
+    prio = (W.counter_values(19, 0, small.faults.size) >> np.uint64(52)).astype(np.float32)
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, lockstep=1,
+               light_cap=light_cap, monitor_rate=2.0)
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, lockstep=1,
+               light_cap=light_cap, priority=prio, unified=1, monitor_rate=1.0)
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, False, lockstep=1, light_cap=light_cap)
+
+
 def test_two_d_unified_medium_full_size():
     w = W.medium()
     _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, monitor_rate=2.0, light_cap=4, unified=1)
