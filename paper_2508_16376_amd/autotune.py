@@ -30,20 +30,21 @@ import numpy as np
 from . import riros
 
 # Descent order: the monitor and capacity first (they decide how much work
-# reaches the structural path), then whether idle wavefronts take it during
-# the light launch, then occupancy and sharing.
+# reaches the structural path), then whether light lanes start their cycles
+# in step, whether idle wavefronts take handed-over work during the light
+# launch, then occupancy, sharing and the structural workgroup size.
 SPACE = {
     "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
     "light_cap": [4, 8],
+    "lockstep": [1, 0],
     "unified": [1, 0],
     "waves_per_cu": [8, 12, 16],
     "struct_share": [1, 2, 4],
     "heavy_wg": [64, 128, 256],
-    "lockstep": [0, 1],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
-           "heavy_wg": 64, "lockstep": 0, "heavy_quantile": None}
+           "heavy_wg": 64, "lockstep": 1, "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:

@@ -16,7 +16,7 @@ def test_descent_finds_the_coordinatewise_minimum():
     t = autotune.Autotuner()
     best, bt = t._descend(cost, with_priority=True)
     assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 1,
-                    "heavy_wg": 128, "lockstep": 0, "heavy_quantile": 0.99}
+                    "heavy_wg": 128, "lockstep": 1, "heavy_quantile": 0.99}
     assert bt == 0
     # every candidate is a point of the space; the descent times no point
     # twice, and then the three fastest points are timed twice more each
