@@ -32,10 +32,12 @@ sys.path.insert(0, ROOT)
 from paper_2508_16376_amd import autotune, predictor, riros  # noqa: E402
 from paper_2508_16376_amd import workloads as W  # noqa: E402
 
-# Published MI355X peaks: HBM3E 8 TB/s; int32 vector ALU 256 compute units x
-# 64 lanes a clock x 2.4 GHz (no packed int32 forms).
+# Published MI355X peaks: HBM3E 8 TB/s.  The int32 vector-ALU peak follows
+# from the published 157.3 TFLOP/s FP32 vector rate, 256 compute units x 128
+# lanes a clock x 2 flops (an FMA) x 2.4 GHz: 128 single-cycle int32 lane
+# operations a clock per compute unit (the probe measures about 70% of it).
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # Bytes of the byte model: 4 per word (riros_sim_opts.words counts the words
 # each fault must touch: its site's golden word per simulated cycle, k + 2
 # per event at a node with k operands, 2 more per divergent register, every
