@@ -203,6 +203,24 @@ typedef struct {
                               lanes of a wavefront (faults of one node or one template,
                               when ordered by priority) walk their frontiers in step; 0 =
                               every lane runs on.  Never changes a result */
+    int32_t deal;          /* TWO_D: 0 = light faults are taken in queue order (with
+                              priorities: descending, so the first wavefronts take
+                              the heaviest 64 each); 4, 8, 16 or 32 = the first
+                              64 x (resident wavefronts) queue positions are dealt
+                              out in groups of `deal` consecutive faults, so that a
+                              wavefront's first 64 lanes take one group of each of
+                              64 / deal priority strata: the heavy head of the
+                              order spreads over every wavefront of the launch
+                              (the longest-first deal of the paper's load
+                              balancing, Sec. IV-C).  Never changes a result */
+    int32_t head_lanes;    /* TWO_D: 0 = a wavefront refills any idle lane (up to its
+                              share of the list) at once; 1..64 = its first take is
+                              head_lanes faults, and it takes no more until all of
+                              them are finished (its other lanes idle meanwhile), so
+                              the head of a descending order (the faults predicted
+                              heaviest) runs head_lanes to a wavefront, beside faults
+                              of its own kind only, on up to 64 / head_lanes times
+                              more wavefronts.  Never changes a result */
 } riros_sim_opts;
 
 typedef struct {

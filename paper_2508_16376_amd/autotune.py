@@ -32,7 +32,9 @@ from . import riros
 # Descent order: the monitor and capacity first (they decide how much work
 # reaches the structural path), then whether light lanes start their cycles
 # in step, whether idle wavefronts take handed-over work during the light
-# launch, then occupancy, sharing and the structural workgroup size.
+# launch, then occupancy, sharing and the structural workgroup size, and
+# how the head of the light queue spreads over the wavefronts (dealt out, or
+# taken a few to a wavefront).
 SPACE = {
     "monitor_rate": [0.0, 1.0, 2.0, 4.0, 8.0],
     "light_cap": [4, 8],
@@ -41,10 +43,13 @@ SPACE = {
     "waves_per_cu": [8, 12, 16],
     "struct_share": [1, 2, 4],
     "heavy_wg": [64, 128, 256],
+    "deal": [0, 8, 32],
+    "head_lanes": [0, 32, 16],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
-           "heavy_wg": 64, "lockstep": 1, "heavy_quantile": None}
+           "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
+           "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -59,7 +64,8 @@ def _opts(p, priority):
         theta = float(np.quantile(priority, p["heavy_quantile"]))
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
             "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0),
-            "heavy_wg": p.get("heavy_wg", 0), "lockstep": p.get("lockstep", 0), "theta": theta}
+            "heavy_wg": p.get("heavy_wg", 0), "lockstep": p.get("lockstep", 0), "deal": p.get("deal", 0),
+            "head_lanes": p.get("head_lanes", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):

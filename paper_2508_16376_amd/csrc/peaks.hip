@@ -88,9 +88,9 @@ int riros_peak_hbm(uint64_t bytes, int reps, double* gbs, void* stream)
         hipEventCreate(&e1) != hipSuccess)
         rc = -4;
     for (int r = 0; rc == 0 && r <= reps; ++r) {
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL(k_stream, dim3(blocks), dim3(256), 0, s, src, dst, n);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         float ms = 0.f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = -4;
         if (r > 0) best = std::min(best, ms);   // the first copy also loads the code object
@@ -120,9 +120,9 @@ int riros_peak_valu(int reps, double* ops_per_s, void* stream)
     float best = 1e30f;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -4;
     for (int r = 0; rc == 0 && r <= reps; ++r) {
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL(k_valu, dim3(blocks), dim3(256), 0, s, 12345u + (uint32_t)r, out);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         float ms = 0.f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = -4;
         if (r > 0) best = std::min(best, ms);

@@ -40,6 +40,16 @@ bool valid_heavy_wg(int32_t v)
     return v == 0 || v == 64 || v == 128 || v == 256;
 }
 
+bool valid_deal(int32_t v)
+{
+    return v == 0 || v == 4 || v == 8 || v == 16 || v == 32;
+}
+
+bool valid_head_lanes(int32_t v)
+{
+    return v >= 0 && v <= 64;
+}
+
 int hip_err(hipError_t e, const char* what)
 {
     char buf[256];
@@ -398,10 +408,12 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         return set_err(RIROS_EINVAL, "unknown mode");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
-        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg))
+        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg) || !valid_deal(opts->deal) ||
+        !valid_head_lanes(opts->head_lanes))
         return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, "
-                                     "light_cap not 0, 4, 8 or 16, struct_share not 0, 1, 2 or 4, or heavy_wg "
-                                     "not 0, 64, 128 or 256)");
+                                     "light_cap not 0, 4, 8 or 16, struct_share not 0, 1, 2 or 4, heavy_wg "
+                                     "not 0, 64, 128 or 256, deal not 0, 4, 8, 16 or 32, or head_lanes not "
+                                     "in 0..64)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -518,6 +530,8 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.heavy_wg = opts->heavy_wg > 0 ? opts->heavy_wg : 64;
         p.w32 = im.max_width <= 32;
         p.lockstep = opts->lockstep ? 1 : 0;
+        p.deal = (uint32_t)opts->deal;
+        p.head_lanes = (uint32_t)opts->head_lanes;
         p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
@@ -730,7 +744,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         return set_err(RIROS_EINVAL, "campaigns run in RIROS_MODE_TWO_D with host-side inputs");
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
-        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg))
+        !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg) || !valid_deal(opts->deal) ||
+        !valid_head_lanes(opts->head_lanes))
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
@@ -866,6 +881,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.heavy_wg = opts->heavy_wg > 0 ? (uint32_t)opts->heavy_wg : 64u;
     p.w32 = Wmax <= 32;
     p.lockstep = opts->lockstep ? 1 : 0;
+    p.deal = (uint32_t)opts->deal;
+    p.head_lanes = (uint32_t)opts->head_lanes;
     p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);

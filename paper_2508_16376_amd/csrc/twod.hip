@@ -208,6 +208,31 @@ __device__ __forceinline__ uint64_t site_words(int drop, uint32_t det, uint32_t 
     return cycles * (width > 32 ? 2u : 1u);
 }
 
+// How light lanes take and run their faults (all of it only changes the
+// schedule, never a result).
+struct LanePolicy {
+    int lockstep;          // a lane about to start a cycle waits while another lane of its wavefront is inside one
+    uint32_t deal;         // 0, or the group size g of the dealt queue head (a power of two, 4 to 32)
+    uint32_t head_lanes;   // 0, or the size of a wavefront's first take, after which it takes nothing until
+                           // that batch is finished
+};
+
+// Light-queue position p -> the queue index it takes, when the head of the
+// queue is dealt out (gshift = log2 of the group size g).  The first
+// 64 x chunks positions are read as chunks rows of 64 (a row is what one
+// wavefront takes first: its 64 lanes): lane l of row c takes group
+// (l / g) * chunks + c of the queue, element l % g.  Row c thus holds group c
+// of each of the 64 / g strata of chunks x g consecutive faults, so the
+// heaviest faults of a descending order spread over every wavefront instead
+// of filling the first ones.  A bijection of [0, 64 x chunks); later
+// positions, and every position when chunks = 0, map to themselves.
+__device__ __forceinline__ uint32_t dealt(uint32_t p, uint32_t gshift, uint32_t chunks)
+{
+    if (p >= chunks * 64u) return p;
+    const uint32_t c = p >> 6, l = p & 63u;
+    return (((l >> gshift) * chunks + c) << gshift) | (l & ((1u << gshift) - 1u));
+}
+
 // Phase 2: light faults one per lane.  A lane with no divergent register
 // skips straight to the next cycle in which its site is excited (the site's
 // bit differs from the stuck value), reading 64 cycles of that bit with one
@@ -222,7 +247,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                             uint32_t nlight, const uint32_t* __restrict__ lorder, TwoDCounters* ctr,
                             uint32_t* __restrict__ esc, int drop, uint32_t* __restrict__ detect_out,
                             uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out,
-                            uint32_t lanes, uint32_t rate_num, int lockstep)
+                            uint32_t lanes, uint32_t rate_num, LanePolicy lp)
 {
     // Register next-state deltas: a pipeline keeps one per divergent stage.
     // Batched lanes hold their design's pointers in registers, so they keep
@@ -230,6 +255,16 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     constexpr int CR = BATCH ? C / 2 : (C == 4 ? 4 : (C == 8 ? 6 : 8));
     constexpr uint32_t kPre = 4;
     const uint32_t lane = threadIdx.x & 63;
+    // Dealing (deal = g > 0): one row of 64 queue positions per wavefront of
+    // the launch, as far as the queue reaches.
+    const uint32_t chunks = lp.deal ? min(gridDim.x * (blockDim.x >> 6), nlight >> 6) : 0u;
+    const uint32_t gshift = lp.deal ? (uint32_t)__builtin_ctz(lp.deal) : 0u;
+    // Head batch (head_lanes = h > 0): the wavefront's first take is h faults
+    // (with priorities, h of the heaviest), and it takes no more until all of
+    // them are finished, so the heaviest faults run h to a wavefront, beside
+    // faults of their own kind only, on up to 64 / h times more wavefronts.
+    // 0: first take; 1: holding the head batch; 2: refilling freely.
+    uint32_t hstate = lp.head_lanes ? 0u : 2u;
     // One design: uniform for the whole wave.  Batched: per lane, per fault.
     LaneDesign d = lane_design(src.d, src.g);
 
@@ -258,7 +293,9 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         // Refill idle lanes from the light queue (one atomic per wave); only
         // the first `lanes` lanes take work, so that light faults spread over
         // every wavefront of the grid.
-        const bool need = fi == kNone && lane < lanes;
+        if (hstate == 1 && __ballot(fi != kNone) == 0) hstate = 2;
+        const uint32_t cap = hstate == 2 ? lanes : min(lanes, lp.head_lanes);
+        const bool need = fi == kNone && lane < cap && hstate != 1;
         const uint64_t needm = __ballot(need && !exhausted);
         if (needm) {
             const uint32_t k = (uint32_t)__popcll(needm);
@@ -279,7 +316,8 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             if (need) {
                 const uint32_t idx = base + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
                 if (idx < nlight) {
-                    fi = lorder ? lorder[idx] : idx;
+                    const uint32_t q = dealt(idx, gshift, chunks);
+                    fi = lorder ? lorder[q] : q;
                     if (BATCH) {
                         const uint32_t k = src.did[fi];
                         d = lane_design(src.td[k], src.tg[k]);
@@ -306,6 +344,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 }
             }
         }
+        if (hstate == 0) hstate = 1;
         if (__ballot(fi != kNone) == 0) break;
         if (fi == kNone) continue;
         // Lockstep (optional): a lane about to start a cycle waits while
@@ -314,7 +353,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         // shape (faults of one node, or of one template) in step: the same
         // branches, and records and golden lines shared between lanes.
         const uint64_t inside = __ballot(in_cycle);
-        if (lockstep && !in_cycle && inside != 0) continue;
+        if (lp.lockstep && !in_cycle && inside != 0) continue;
 
         bool esc_now = false;
         // Record a divergent node: keep its delta, schedule its users, stage
@@ -594,7 +633,7 @@ __global__ __launch_bounds__(STRUCT ? 64 * kMaxShare : 64) __attribute__((amdgpu
 void k_twod_a(
     DesignSrc src, MaxShape mx, const riros_fault* __restrict__ faults, uint32_t F,
     const uint32_t* __restrict__ order, TwoDCounters* ctr, uint32_t* __restrict__ esc, int drop, PlainWorkspace ws,
-    uint32_t rate_num, int unified, int group_heavy, int lockstep, uint32_t* __restrict__ detect_out,
+    uint32_t rate_num, int unified, int group_heavy, LanePolicy lp, uint32_t* __restrict__ detect_out,
     uint64_t* __restrict__ events_out, uint64_t* __restrict__ words_out)
 {
     if constexpr (STRUCT) {
@@ -636,7 +675,7 @@ void k_twod_a(
         const uint32_t lanes = min(64u, max(1u, (nlight + waves - 1) / waves));
         light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(
             src, faults, nlight, order ? order + nh : nullptr, ctr, esc, drop, detect_out, events_out, words_out, lanes,
-            rate_num, lockstep);
+            rate_num, lp);
         if (unified && wave == 0)
             drain_handover<BATCH>(src, faults, F, nlight, ctr, esc, drop, s, slots, regs, stamp0, detect_out,
                                   events_out, words_out);
@@ -644,7 +683,7 @@ void k_twod_a(
         const uint32_t lanes = min(64u, max(1u, (F + gridDim.x - 1) / gridDim.x));
         light_phase<C, BATCH, std::conditional_t<W32, uint32_t, uint64_t>>(src, faults, F, order, ctr, esc, drop,
                                                                           detect_out, events_out, words_out, lanes,
-                                                                          rate_num, lockstep);
+                                                                          rate_num, lp);
     }
 }
 
@@ -920,8 +959,9 @@ static void launch_b(uint32_t wg, uint32_t blocks, size_t lds, hipStream_t s, co
 template <int C, bool BATCH, bool W32>
 static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const riros_fault* faults, uint32_t F,
                                 const uint32_t* order, bool heavy, int unified, int share, uint32_t heavy_wg,
-                                int lockstep, TwoDCounters* ctr, uint32_t* esc, int drop, const PlainWorkspace& ws,
-                                uint64_t span, uint32_t blocks, uint32_t rate_num, uint32_t* detect, uint64_t* events,
+                                LanePolicy lp, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                const PlainWorkspace& ws, uint64_t span, uint32_t blocks, uint32_t rate_num,
+                                uint32_t* detect, uint64_t* events,
                                 uint64_t* words, hipStream_t s)
 {
     const size_t lds = lds_bytes_a(mx), ldsb = lds_bytes_b(mx);
@@ -934,11 +974,11 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
         hipLaunchKernelGGL(k_fill_u32, dim3((F + kTicketPad + 255) / 256), dim3(256), 0, s, esc, F + kTicketPad, kNone);
     if (structural) {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, true, W32>), dim3(ga.blocks), dim3(ga.threads), lds, s, src, mx, faults, F,
-                           order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, lockstep, detect, events,
-                           words);
+                           order, ctr, esc, drop, ws, rate_num, unified, heavy_wg > 64 ? 1 : 0, lp, detect,
+                           events, words);
     } else {
         hipLaunchKernelGGL((k_twod_a<C, BATCH, false, W32>), dim3(ga.blocks), dim3(64), 0, s, src, mx, faults, F, order,
-                           ctr, esc, drop, ws, rate_num, 0, 0, lockstep, detect, events, words);
+                           ctr, esc, drop, ws, rate_num, 0, 0, lp, detect, events, words);
     }
     const uint32_t wgb = heavy_wg > 64 ? heavy_wg : 64u;
     const uint32_t bb = resident_blocks(kernel_b<BATCH>(wgb), ldsb, blocks, wgb);
@@ -951,12 +991,14 @@ static hipError_t launch_twod_c(const DesignSrc& src, const MaxShape& mx, const 
 template <bool BATCH>
 static hipError_t launch_twod_any(int cap, bool w32, const DesignSrc& src, const MaxShape& mx,
                                   const riros_fault* faults, uint32_t F, const uint32_t* order, bool heavy, int unified,
-                                  int share, uint32_t heavy_wg, int lockstep, TwoDCounters* ctr, uint32_t* esc, int drop,
+                                  int share, uint32_t heavy_wg, LanePolicy lp, TwoDCounters* ctr,
+                                  uint32_t* esc, int drop,
                                   const PlainWorkspace& ws, uint64_t span, uint32_t blocks, uint32_t rate_num,
                                   uint32_t* detect, uint64_t* events, uint64_t* words, hipStream_t s)
 {
 #define RIROS_TWOD_C(CAP, W)                                                                                       \
-    launch_twod_c<CAP, BATCH, W>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, lockstep, ctr, esc, drop,   \
+    launch_twod_c<CAP, BATCH, W>(src, mx, faults, F, order, heavy, unified, share, heavy_wg, lp, ctr, esc,               \
+                                 drop,                                                                                \
                                  ws, span,                                                                            \
                                  blocks, rate_num, detect, events, words, s)
     switch (cap) {
@@ -1035,7 +1077,9 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
     hipError_t e = launch_twod_any<false>(p.light_cap, p.w32, src, mx, faults, F, order, heavy, p.unified, p.share,
-                                          (uint32_t)p.heavy_wg, p.lockstep, ctr, esc, drop, heavy_ws, span, blocks,
+                                          (uint32_t)p.heavy_wg, LanePolicy{p.lockstep, p.deal, p.head_lanes}, ctr,
+                                          esc, drop, heavy_ws, span,
+                                          blocks,
                                           rate_num,
                                           detect, events, words, s);
     if (e != hipSuccess) { err = std::string("two-dimensional kernels: ") + hipGetErrorString(e); return RIROS_EDEVICE; }
@@ -1099,7 +1143,9 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
 #define RIROS_LAUNCH_A(CAP, HV, L, W)                                                                        \
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV, W>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,  \
                        b.faults, b.F, b.order,                                                                   \
-                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0, b.lockstep, b.detect,  \
+                       ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0,                       \
+                       LanePolicy{b.lockstep, b.deal, b.head_lanes},                                             \
+                       b.detect,                                                                                  \
                        b.events,                                                                                  \
                        b.words)
     if (b.unified)

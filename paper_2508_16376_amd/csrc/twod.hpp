@@ -26,6 +26,8 @@ struct TwoDParams {
     int heavy_wg = 64;          // threads that simulate one structural fault (64, 128 or 256)
     bool w32 = false;           // every node at most 32 bits wide: light lanes keep 32-bit values
     int lockstep = 0;           // light lanes of a wavefront start their cycles together
+    uint32_t deal = 0;          // light queue dealt in groups of this many faults (0 = queue order)
+    uint32_t head_lanes = 0;    // a wavefront's first take, finished before it takes more (0 = off)
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -67,6 +69,8 @@ struct BatchPlan {
     uint32_t heavy_wg = 64;   // threads per structural fault (see riros_sim_opts.heavy_wg)
     bool w32 = false;         // every node of every design at most 32 bits wide (32-bit light lanes)
     int lockstep = 0;         // light lanes of a wavefront start their cycles together
+    uint32_t deal = 0;        // light queue dealt in groups of this many faults (0 = queue order)
+    uint32_t head_lanes = 0;  // a wavefront's first take, finished before it takes more (0 = off)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;

@@ -69,6 +69,14 @@ def test_full_size_every_fault(name):
                            theta=float(np.quantile(pred, 0.99)), monitor_rate=1.0, light_cap=8, waves_per_cu=12,
                            unified=1)
     _compare(name + " two-dimensional", w, *_device_run(d, g, w, opts), odet, oev, owk)
+    # The kind of schedule the benchmark's tuner picks on these lists: no
+    # heavy prefix, capacity 4, lanes in lockstep, the queue's head dealt out
+    # in groups of 8, workgroups of four wavefronts sharing one structural
+    # workspace.
+    print(f"[full-size] {name}: lockstep, dealt queue", flush=True)
+    opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio, light_cap=4, waves_per_cu=12,
+                           unified=1, struct_share=4, lockstep=1, deal=8)
+    _compare(name + " two-dimensional (lockstep, dealt)", w, *_device_run(d, g, w, opts), odet, oev, owk)
     print(f"[full-size] {name}: plain", flush=True)
     _compare(name + " plain", w, *_device_run(d, g, w, riros.make_opts(riros.MODE_PLAIN, True, True, stream=s)),
              odet, oev, owk)

@@ -301,6 +301,45 @@ def test_two_d_lockstep_lanes(small, tiny, light_cap):
     _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, False, lockstep=1, light_cap=light_cap)
 
 
+@pytest.mark.parametrize("deal", [4, 8, 32])
+def test_two_d_dealt_light_queue(small, tiny, deal):
+    """The head of the light queue dealt out in groups over every wavefront:
+    one wavefront per compute unit (256 rows of 64 positions, fewer than the
+    4,000 faults: the deal covers part of the queue) and twelve (the queue
+    ends inside the dealt rows), with and without priorities, lockstep on and
+    off, drop on and off."""
+    prio = (W.counter_values(23, 0, small.faults.size) >> np.uint64(50)).astype(np.float32)
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, deal=deal,
+               waves_per_cu=1, light_cap=4, lockstep=1, priority=prio, unified=1)
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, deal=deal,
+               waves_per_cu=12, light_cap=8, monitor_rate=2.0)
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, True, deal=deal, lockstep=1)
+
+
+@pytest.mark.parametrize("head_lanes", [1, 16, 40])
+def test_two_d_head_batch(small, tiny, head_lanes):
+    """A wavefront's first take limited to head_lanes faults, finished before
+    it takes more; with priorities, lockstep and a dealt head, drop on and
+    off, one and twelve wavefronts per compute unit."""
+    prio = (W.counter_values(31, 0, small.faults.size) >> np.uint64(50)).astype(np.float32)
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, head_lanes=head_lanes,
+               waves_per_cu=1, light_cap=4, lockstep=1, priority=prio, unified=1, struct_share=4)
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, head_lanes=head_lanes,
+               deal=8, waves_per_cu=12, light_cap=8, monitor_rate=2.0, priority=prio)
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, True, head_lanes=head_lanes)
+
+
+def test_two_d_dealt_medium_full_size():
+    """50,000 faults over 256 wavefronts: 16,384 dealt positions, then the rest
+    of the queue in order."""
+    w = W.medium()
+    prio = (W.counter_values(29, 0, w.faults.size) >> np.uint64(48)).astype(np.float32)
+    _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, deal=8, waves_per_cu=1, light_cap=4,
+           lockstep=1, unified=1, struct_share=4, priority=prio)
+
+
 def test_two_d_unified_medium_full_size():
     w = W.medium()
     _check(w.design, w.stimulus, w.T, w.faults, riros.MODE_TWO_D, True, monitor_rate=2.0, light_cap=4, unified=1)
@@ -310,7 +349,8 @@ def test_two_d_rejects_bad_options(tiny):
     d = riros.Design(tiny.design)
     g = riros.Golden(d, tiny.stimulus, tiny.T)
     for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}, {"struct_share": 3}, {"struct_share": 8},
-               {"heavy_wg": 96}, {"heavy_wg": 512}):
+               {"heavy_wg": 96}, {"heavy_wg": 512}, {"deal": 2}, {"deal": 12}, {"deal": 64},
+               {"head_lanes": -1}, {"head_lanes": 65}):
         with pytest.raises(riros.RirosError):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
