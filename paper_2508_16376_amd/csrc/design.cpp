@@ -240,6 +240,24 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
         img.max_width = std::max<uint32_t>(img.max_width, o.width);
     }
     img.bp_rows = rows;
+    img.lrec.assign(N, LaneRec{});
+    for (uint32_t i = 0; i < N; ++i) {
+        const NodeRec& r = img.rec[i];
+        LaneRec& l = img.lrec[i];
+        l.op = r.op;
+        l.width = r.width;
+        l.flags = r.flags;
+        l.words = r.words;
+        l.a = r.a;
+        l.b = r.b;
+        l.c = r.c;
+        l.fo0 = r.fo0;
+        l.fo1 = r.fo1;
+        l.rfo0 = r.rfo0;
+        l.rfo1 = r.rfo1;
+        for (uint32_t k = 0; k < 4; ++k) l.u[k] = img.fo[r.fo0 + k];   // padded: always in the table
+        l.r0 = img.rfo[r.rfo0];
+    }
     return RIROS_OK;
 }
 

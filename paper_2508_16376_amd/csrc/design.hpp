@@ -40,6 +40,23 @@ struct NodeRec {
 };
 static_assert(sizeof(NodeRec) == 32, "record layout");
 
+// 64-byte record of the light (one fault per lane) path: the node record
+// plus the first four entries of the node's combinational fan-out and the
+// first register it feeds (the tables' padding where the lists are
+// shorter), so that a lane evaluating the node gets its users in the same
+// round trip as its operands' ids, and only the operands' golden values take
+// a second one.
+struct LaneRec {
+    uint8_t op, width, flags, words;
+    uint32_t a, b, c;
+    uint32_t fo0, fo1;
+    uint32_t rfo0, rfo1;
+    uint32_t u[4];     // fo[fo0 .. fo0 + 3]
+    uint32_t r0;       // rfo[rfo0]
+    uint32_t pad[3];
+};
+static_assert(sizeof(LaneRec) == 64, "lane record layout");
+
 struct Image {
     uint32_t N = 0, L = 0, R = 0, npi = 0;
     std::vector<uint32_t> u2i, i2u;         // user id <-> internal id
@@ -52,6 +69,7 @@ struct Image {
     // fo, fo_pk and rfo end in kFanoutPad zero entries (fo_lvl does not).
     std::vector<uint32_t> po;                   // internal ids, deduplicated
     std::vector<NodeRec> rec;                   // per internal node
+    std::vector<LaneRec> lrec;                  // per internal node, for the light path
     std::vector<uint32_t> bp_off;               // first bit-plane row of each node (prefix sum of widths)
     uint32_t bp_rows = 0;                       // total bit-plane rows (sum of widths)
     uint32_t max_width = 0;                     // widest node

@@ -21,6 +21,7 @@ struct DevDesign {
     const uint32_t* u2i;
     const uint8_t* uwidth;     // width per user node id
     const NodeRec* rec;        // per internal node: descriptor + fan-out ranges
+    const LaneRec* lrec;       // per internal node: the record with its first users inline (light path)
     const uint64_t* fo_pk;     // fan-out entries: user id | user level << 32
     const uint32_t* bp_off;    // per internal node: first bit-plane row
     uint32_t N, L, R, npi;

@@ -208,14 +208,16 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
              *p_rfo_off = nullptr, *p_rfo = nullptr, *p_u2i = nullptr;
     uint8_t* p_uw = nullptr;
     riros::NodeRec* p_rec = nullptr;
+    riros::LaneRec* p_lrec = nullptr;
     uint32_t* p_bp = nullptr;
     uint64_t* p_fopk = nullptr;
-    hipError_t es[13] = {dev_upload(&p_rec, im.rec), dev_upload(&p_bp, im.bp_off), dev_upload(&p_fopk, im.fo_pk),
+    hipError_t es[14] = {dev_upload(&p_rec, im.rec), dev_upload(&p_lrec, im.lrec), dev_upload(&p_bp, im.bp_off),
+        dev_upload(&p_fopk, im.fo_pk),
         dev_upload(&p_desc, im.desc),     dev_upload(&p_lvl, im.lvl_off), dev_upload(&p_level, im.level),
         dev_upload(&p_fo_off, im.fo_off), dev_upload(&p_fo, im.fo),       dev_upload(&p_fo_lvl, im.fo_lvl),
         dev_upload(&p_rfo_off, im.rfo_off), dev_upload(&p_rfo, im.rfo),   dev_upload(&p_u2i, im.u2i),
         dev_upload(&p_uw, uwidth)};
-    for (void* p : {(void*)p_rec, (void*)p_bp, (void*)p_fopk, (void*)p_desc, (void*)p_lvl, (void*)p_level, (void*)p_fo_off, (void*)p_fo, (void*)p_fo_lvl,
+    for (void* p : {(void*)p_rec, (void*)p_lrec, (void*)p_bp, (void*)p_fopk, (void*)p_desc, (void*)p_lvl, (void*)p_level, (void*)p_fo_off, (void*)p_fo, (void*)p_fo_lvl,
                     (void*)p_rfo_off, (void*)p_rfo, (void*)p_u2i, (void*)p_uw})
         if (p) d->owned.push_back(p);
     for (hipError_t x : es)
@@ -225,7 +227,7 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
             return hip_err(x, "design upload");
         }
     d->dev = riros::DevDesign{p_desc, p_lvl, p_level, p_fo_off, p_fo, p_fo_lvl, p_rfo_off, p_rfo, p_u2i, p_uw,
-                              p_rec, p_fopk, p_bp, im.N, im.L, im.R, im.npi, im.bp_rows};
+                              p_rec, p_lrec, p_fopk, p_bp, im.N, im.L, im.R, im.npi, im.bp_rows};
     e = hipMalloc((void**)&d->d_cov, sizeof(riros_coverage));
     if (e == hipSuccess) e = hipMalloc((void**)&d->d_bad, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&d->stamp_dev, sizeof(uint64_t));

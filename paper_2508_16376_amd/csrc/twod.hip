@@ -176,7 +176,7 @@ __device__ __forceinline__ V apply_fault_v(V v, uint32_t bit, uint32_t stuck, ui
 // Per-lane view of a fault's design: everything the light path reads.
 struct LaneDesign {
     const uint32_t* u2i;
-    const NodeRec* rec;
+    const LaneRec* rec;
     const uint32_t* fo;
     const uint32_t* rfo;
     const uint32_t* bp_off;
@@ -187,7 +187,7 @@ struct LaneDesign {
 
 __device__ __forceinline__ LaneDesign lane_design(const DevDesign& d, const GoldenView& g)
 {
-    return LaneDesign{d.u2i, d.rec, d.fo, d.rfo, d.bp_off, g.Gn, g.Bp, g.T, g.TW};
+    return LaneDesign{d.u2i, d.lrec, d.fo, d.rfo, d.bp_off, g.Gn, g.Bp, g.T, g.TW};
 }
 
 // Where a fault's design comes from: the launch's one design, or (batched
@@ -275,8 +275,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     uint64_t exw = 0;
     uint32_t ewb = kNone;
     size_t bprow = 0;
-    NodeRec srec{};
-    uint32_t sf0 = 0, sf1 = 0, sf2 = 0, sf3 = 0;
+    LaneRec srec{};
     bool exhausted = nlight == 0;
     SortedIds<C> pend;
     DeltaSet<C, V> div;
@@ -329,10 +328,6 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     ft0 = f.t0;
                     srec = d.rec[site];
                     bprow = (size_t)(d.bp_off[site] + fbit) * d.TW;
-                    sf0 = d.fo[srec.fo0];
-                    sf1 = d.fo[srec.fo0 + 1];
-                    sf2 = d.fo[srec.fo0 + 2];
-                    sf3 = d.fo[srec.fo0 + 3];
                     t = 0;
                     det = RIROS_UNDETECTED;
                     ev = 0;
@@ -357,18 +352,18 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
 
         bool esc_now = false;
         // Record a divergent node: keep its delta, schedule its users, stage
-        // register next states, note output mismatches.
-        auto on_divergent = [&](uint32_t n, V delta, const NodeRec& r, uint32_t p0, uint32_t p1,
-                                uint32_t p2, uint32_t p3) {
+        // register next states, note output mismatches.  The first four users
+        // and the first register fed come with the node's record.
+        auto on_divergent = [&](uint32_t n, V delta, const LaneRec& r) {
             if (!div.add(n, delta)) { esc_now = true; return; }
             if ((r.flags & DF_PO) && det == RIROS_UNDETECTED) det = t;
             for (uint32_t e = r.fo0; e < r.fo1; ++e) {
                 const uint32_t k = e - r.fo0;
-                const uint32_t u = k < kPre ? pick4(k, p0, p1, p2, p3) : d.fo[e];
+                const uint32_t u = k < kPre ? pick4(k, r.u[0], r.u[1], r.u[2], r.u[3]) : d.fo[e];
                 if (!pend.insert(u)) { esc_now = true; return; }
             }
             for (uint32_t e = r.rfo0; e < r.rfo1; ++e)
-                if (!rnxt.add(d.rfo[e], delta)) { esc_now = true; return; }
+                if (!rnxt.add(e == r.rfo0 ? r.r0 : d.rfo[e], delta)) { esc_now = true; return; }
         };
 
         bool evaluated = false;
@@ -410,7 +405,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 }
                 ev++;
                 wk += srec.words;
-                on_divergent(site, (V)1 << fbit, srec, sf0, sf1, sf2, sf3);
+                on_divergent(site, (V)1 << fbit, srec);
                 evaluated = true;
             } else {
                 // Divergent registers are evaluated first, straight from
@@ -426,11 +421,11 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         }
         if (!evaluated && !esc_now) {
             // Evaluate the lowest pending node (users always have larger ids).
-            // The record, then everything it points at in one round trip:
+            // The record (with the node's first users) and the node's golden
+            // value, then the operands' golden values in one round trip:
             // unconditional loads combined with selects (an operand slot the
             // operator does not read repeats the first operand, or the node
-            // itself; the fan-out table ends in padding), so no load waits
-            // for another.
+            // itself), so no load waits for another.
             uint32_t n = 0;
             if (rk < rcur.n) {
 #pragma unroll
@@ -440,7 +435,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             } else {
                 n = pend.pop_min();
             }
-            const NodeRec r = d.rec[n];
+            const LaneRec r = d.rec[n];
             const uint32_t T = d.T;
             const V gv = gold_at<V>(d.Gn, (size_t)n * T + t);
             const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
@@ -450,7 +445,6 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             const uint32_t i2 = ar > 2 ? r.c : i0;
             V x0 = gold_at<V>(d.Gn, (size_t)i0 * T + t), x1 = gold_at<V>(d.Gn, (size_t)i1 * T + t),
               x2 = gold_at<V>(d.Gn, (size_t)i2 * T + t);
-            const uint32_t p0 = d.fo[r.fo0], p1 = d.fo[r.fo0 + 1], p2 = d.fo[r.fo0 + 2], p3 = d.fo[r.fo0 + 3];
             V delta = 0;
             bool din = false;
             if (r.op == RIROS_OP_REG) {
@@ -467,7 +461,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 ev++;
                 wk += (r.op == RIROS_OP_REG && din) ? 2u * r.words : r.words;
             }
-            if (dout) on_divergent(n, delta, r, p0, p1, p2, p3);
+            if (dout) on_divergent(n, delta, r);
         }
 
         // Monitor: a fault averaging more than rate_num/4 events per cycle after
