@@ -257,6 +257,11 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
         l.rfo1 = r.rfo1;
         for (uint32_t k = 0; k < 4; ++k) l.u[k] = img.fo[r.fo0 + k];   // padded: always in the table
         l.r0 = img.rfo[r.rfo0];
+        const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
+        const uint32_t ar = comb ? (uint32_t)op_arity(r.op) : 0u;
+        l.o[0] = ar > 0 ? r.a : i;
+        l.o[1] = ar > 1 ? r.b : l.o[0];
+        l.o[2] = ar > 2 ? r.c : l.o[0];
     }
     return RIROS_OK;
 }

@@ -45,7 +45,10 @@ static_assert(sizeof(NodeRec) == 32, "record layout");
 // first register it feeds (the tables' padding where the lists are
 // shorter), so that a lane evaluating the node gets its users in the same
 // round trip as its operands' ids, and only the operands' golden values take
-// a second one.
+// a second one.  o[3] are the nodes whose golden values the evaluation reads
+// as operands x0, x1, x2: the operands an operator has, the first operand
+// again in the slots it does not read, and the node itself for a register,
+// input or constant (so the three loads need no decision).
 struct LaneRec {
     uint8_t op, width, flags, words;
     uint32_t a, b, c;
@@ -53,7 +56,7 @@ struct LaneRec {
     uint32_t rfo0, rfo1;
     uint32_t u[4];     // fo[fo0 .. fo0 + 3]
     uint32_t r0;       // rfo[rfo0]
-    uint32_t pad[3];
+    uint32_t o[3];
 };
 static_assert(sizeof(LaneRec) == 64, "lane record layout");
 

@@ -420,48 +420,74 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             in_cycle = true;
         }
         if (!evaluated && !esc_now) {
-            // Evaluate the lowest pending node (users always have larger ids).
-            // The record (with the node's first users) and the node's golden
-            // value, then the operands' golden values in one round trip:
-            // unconditional loads combined with selects (an operand slot the
-            // operator does not read repeats the first operand, or the node
-            // itself), so no load waits for another.
-            uint32_t n = 0;
+            // Evaluate the next node (registers of the cycle first, then the
+            // lowest pending node: users always have larger ids) and, in the
+            // same iteration, the node after it, when that one is still the
+            // next once the first's users are scheduled: two registers of a
+            // cycle never depend on each other, and a pending node depends on
+            // no node other than smaller pending ones and the registers.  For
+            // both: the record (with the node's first users) and the node's
+            // golden value, then the operands' golden values in one round
+            // trip, from the record's operand slots (a slot the operator does
+            // not read repeats the first operand, or the node itself), so no
+            // load waits for another.  Pairs only with 32-bit values: 64-bit
+            // lanes have no registers to spare for the second node.
+            constexpr bool kPair = sizeof(V) == 4;
+            uint32_t n0 = 0, n1 = kNone;
+            bool n1_reg = false;
             if (rk < rcur.n) {
 #pragma unroll
-                for (int k = 0; k < CR; ++k)
-                    if ((uint32_t)k == rk) n = rcur.id[k];
+                for (int k = 0; k < CR; ++k) {
+                    if ((uint32_t)k == rk) n0 = rcur.id[k];
+                    if (kPair && (uint32_t)k == rk + 1 && rk + 1 < rcur.n) {
+                        n1 = rcur.id[k];
+                        n1_reg = true;
+                    }
+                }
+                if (kPair && !n1_reg && pend.n > 0) n1 = pend.v[0];
                 rk++;
             } else {
-                n = pend.pop_min();
+                n0 = pend.pop_min();
+                if (kPair && pend.n > 0) n1 = pend.v[0];
             }
-            const LaneRec r = d.rec[n];
             const uint32_t T = d.T;
-            const V gv = gold_at<V>(d.Gn, (size_t)n * T + t);
-            const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
-            const int ar = comb ? dev_arity(r.op) : 0;
-            const uint32_t i0 = ar > 0 ? r.a : n;
-            const uint32_t i1 = ar > 1 ? r.b : i0;
-            const uint32_t i2 = ar > 2 ? r.c : i0;
-            V x0 = gold_at<V>(d.Gn, (size_t)i0 * T + t), x1 = gold_at<V>(d.Gn, (size_t)i1 * T + t),
-              x2 = gold_at<V>(d.Gn, (size_t)i2 * T + t);
-            V delta = 0;
-            bool din = false;
-            if (r.op == RIROS_OP_REG) {
-                delta = rcur.find(n, din);
-            } else if (comb) {
-                x0 ^= div.find(i0, din);
-                if (ar > 1) x1 ^= div.find(i1, din);
-                if (ar > 2) x2 ^= div.find(i2, din);
-                delta = apply_op_v<V>(r.op, r.width, r.b, r.c, x0, x1, x2) ^ gv;
+            const uint32_t m1 = n1 != kNone ? n1 : n0;
+            const LaneRec r0 = d.rec[n0];
+            const LaneRec r1 = d.rec[m1];
+            const V g0 = gold_at<V>(d.Gn, (size_t)n0 * T + t);
+            const V g1 = gold_at<V>(d.Gn, (size_t)m1 * T + t);
+            const V x00 = gold_at<V>(d.Gn, (size_t)r0.o[0] * T + t), x01 = gold_at<V>(d.Gn, (size_t)r0.o[1] * T + t),
+                    x02 = gold_at<V>(d.Gn, (size_t)r0.o[2] * T + t);
+            const V x10 = gold_at<V>(d.Gn, (size_t)r1.o[0] * T + t), x11 = gold_at<V>(d.Gn, (size_t)r1.o[1] * T + t),
+                    x12 = gold_at<V>(d.Gn, (size_t)r1.o[2] * T + t);
+            auto evaluate = [&](uint32_t n, const LaneRec& r, V gv, V x0, V x1, V x2) {
+                const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
+                V delta = 0;
+                bool din = false;
+                if (r.op == RIROS_OP_REG) {
+                    delta = rcur.find(n, din);
+                } else if (comb) {
+                    // A repeated slot finds what the first one found: din and
+                    // the operands the operator reads are exact.
+                    x0 ^= div.find(r.o[0], din);
+                    x1 ^= div.find(r.o[1], din);
+                    x2 ^= div.find(r.o[2], din);
+                    delta = apply_op_v<V>(r.op, r.width, r.b, r.c, x0, x1, x2) ^ gv;
+                }
+                if (n == site) delta = apply_fault_v<V>(gv ^ delta, fbit, fval, t, ft0) ^ gv;
+                const bool dout = delta != 0;
+                if (din || dout) {
+                    ev++;
+                    wk += (r.op == RIROS_OP_REG && din) ? 2u * r.words : r.words;
+                }
+                if (dout) on_divergent(n, delta, r);
+            };
+            evaluate(n0, r0, g0, x00, x01, x02);
+            if (kPair && n1 != kNone && !esc_now && (n1_reg || (rk >= rcur.n && pend.n > 0 && pend.v[0] == n1))) {
+                if (n1_reg) rk++;
+                else (void)pend.pop_min();
+                evaluate(n1, r1, g1, x10, x11, x12);
             }
-            if (n == site) delta = apply_fault_v<V>(gv ^ delta, fbit, fval, t, ft0) ^ gv;
-            const bool dout = delta != 0;
-            if (din || dout) {
-                ev++;
-                wk += (r.op == RIROS_OP_REG && din) ? 2u * r.words : r.words;
-            }
-            if (dout) on_divergent(n, delta, r);
         }
 
         // Monitor: a fault averaging more than rate_num/4 events per cycle after
