@@ -283,6 +283,16 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     pend.n = div.n = rcur.n = rnxt.n = 0;
 
     bool finished = false;   // this lane finished or handed over a fault in the last iteration
+    // Lanes with 32-bit values and capacity 4 evaluate two nodes per
+    // iteration (see below) and keep the record of the last register they
+    // evaluated (creg, not the site): when that register is the first
+    // divergent one of the next cycle, as a latent accumulator's is in every
+    // cycle, it is evaluated at the cycle start without a load, and its users
+    // go into the same iteration's pair.  Wider values or larger sets leave
+    // no registers for either.
+    constexpr bool kPair = sizeof(V) == 4 && C <= 4;
+    uint32_t creg = kNone;
+    LaneRec crec{};
     for (;;) {
         // Count the faults finished in the last iteration out of flight (one
         // atomic per wave), after their hand-overs were performed.
@@ -332,6 +342,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                     det = RIROS_UNDETECTED;
                     ev = 0;
                     wk = 0;
+                    creg = kNone;
                     pend.n = div.n = rcur.n = rnxt.n = 0;
                     rk = 0;
                     in_cycle = false;
@@ -416,6 +427,14 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 bool site_reg = false;
                 (void)rcur.find(site, site_reg);
                 if (!site_reg && !pend.insert(site)) esc_now = true;
+                if (kPair && !esc_now && creg != kNone && rcur.id[0] == creg) {
+                    // A register's evaluation: its delta is its staged next
+                    // state (an event with a divergent input and output).
+                    ev++;
+                    wk += 2u * crec.words;
+                    on_divergent(creg, rcur.dx[0], crec);
+                    rk = 1;
+                }
             }
             in_cycle = true;
         }
@@ -430,9 +449,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             // golden value, then the operands' golden values in one round
             // trip, from the record's operand slots (a slot the operator does
             // not read repeats the first operand, or the node itself), so no
-            // load waits for another.  Pairs only with 32-bit values: 64-bit
-            // lanes have no registers to spare for the second node.
-            constexpr bool kPair = sizeof(V) == 4;
+            // load waits for another.
             uint32_t n0 = 0, n1 = kNone;
             bool n1_reg = false;
             if (rk < rcur.n) {
@@ -466,6 +483,10 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 bool din = false;
                 if (r.op == RIROS_OP_REG) {
                     delta = rcur.find(n, din);
+                    if (kPair && n != site) {
+                        creg = n;
+                        crec = r;
+                    }
                 } else if (comb) {
                     // A repeated slot finds what the first one found: din and
                     // the operands the operator reads are exact.
