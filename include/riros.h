@@ -112,7 +112,8 @@ void riros_free_design(riros_design d);
  * primary-input values of cycle t (masked to each PI's width on use).  The
  * trace is kept in three layouts (cycle-major, node-major and one bit-plane
  * per node bit), about 16*T*num_nodes + T*sum(widths)/8 bytes of device
- * memory.  Errors: RIROS_EINVAL
+ * memory, plus 4*T*num_nodes for a 32-bit node-major copy when no node is
+ * wider than 32 bits.  Errors: RIROS_EINVAL
  * (T == 0, NULL pointers), RIROS_ENOMEM, RIROS_EDEVICE.  *out is a new handle. */
 int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream,
                      riros_golden* out);

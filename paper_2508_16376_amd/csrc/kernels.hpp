@@ -40,10 +40,14 @@ struct GoldenView {
     const uint64_t* Bp;
     uint32_t T;
     uint32_t TW;   // words per bit-plane row = ceil(T / 64)
+    // Node-major 32-bit copy Gn32[n][t] when no node is wider than 32 bits
+    // (else NULL): the light path's golden reads, a 128-byte line holding 32
+    // cycles of a node instead of 16.
+    const uint32_t* Gn32;
 };
 
 hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t T, uint64_t* Gn, uint64_t* Bp,
-                                 hipStream_t s);
+                                 uint32_t* Gn32, hipStream_t s);
 
 // Per-node faulty value with the cycle stamp that makes it valid.
 struct __attribute__((aligned(16))) Slot {

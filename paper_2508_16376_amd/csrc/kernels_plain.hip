@@ -80,7 +80,7 @@ hipError_t launch_golden_many(uint32_t n, const DevDesign* td, const GoldenJob* 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_golden_layouts(DevDesign d, const uint64_t* __restrict__ G, uint32_t T,
                                                        uint32_t TW, uint64_t* __restrict__ Gn,
-                                                       uint64_t* __restrict__ Bp)
+                                                       uint64_t* __restrict__ Bp, uint32_t* __restrict__ Gn32)
 {
     __shared__ uint64_t tile[64][65];
     const uint32_t lane = threadIdx.x;
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(64) void k_golden_layouts(DevDesign d, const uint64
         const uint32_t n = n0 + j;
         const uint64_t v = tile[lane][j];
         if (tv) Gn[(size_t)n * T + t] = v;
+        if (tv && Gn32) Gn32[(size_t)n * T + t] = (uint32_t)v;
         const uint32_t w = d.rec[n].width;
         const uint32_t row0 = d.bp_off[n];
         uint64_t mine = 0;
@@ -110,10 +111,10 @@ __global__ __launch_bounds__(64) void k_golden_layouts(DevDesign d, const uint64
 }
 
 hipError_t launch_golden_layouts(const DevDesign& d, const uint64_t* G, uint32_t T, uint64_t* Gn, uint64_t* Bp,
-                                 hipStream_t s)
+                                 uint32_t* Gn32, hipStream_t s)
 {
     const uint32_t TW = (T + 63) / 64;
-    hipLaunchKernelGGL(k_golden_layouts, dim3((d.N + 63) / 64, TW), dim3(64), 0, s, d, G, T, TW, Gn, Bp);
+    hipLaunchKernelGGL(k_golden_layouts, dim3((d.N + 63) / 64, TW), dim3(64), 0, s, d, G, T, TW, Gn, Bp, Gn32);
     return hipGetLastError();
 }
 

@@ -133,8 +133,9 @@ struct riros_golden_s {
     uint64_t* G = nullptr;    // row-major [T][N]
     uint64_t* Gn = nullptr;   // node-major [N][T]
     uint64_t* Bp = nullptr;   // bit-planes [bp_rows][ceil(T/64)]
+    uint32_t* Gn32 = nullptr; // node-major 32-bit copy [N][T] when no node is wider than 32 bits
     uint64_t* stim = nullptr; // the stimulus [T][npi] (a campaign graph may recompute the trace)
-    riros::GoldenView view() const { return riros::GoldenView{G, Gn, Bp, T, (T + 63) / 64}; }
+    riros::GoldenView view() const { return riros::GoldenView{G, Gn, Bp, T, (T + 63) / 64, Gn32}; }
 };
 
 static void free_golden_mem(riros_golden g)
@@ -142,8 +143,10 @@ static void free_golden_mem(riros_golden g)
     if (g->G) (void)hipFree(g->G);
     if (g->Gn) (void)hipFree(g->Gn);
     if (g->Bp) (void)hipFree(g->Bp);
+    if (g->Gn32) (void)hipFree(g->Gn32);
     if (g->stim) (void)hipFree(g->stim);
     g->G = g->Gn = g->Bp = g->stim = nullptr;
+    g->Gn32 = nullptr;
 }
 
 // Device buffers of one golden trace and its uploaded stimulus.
@@ -157,6 +160,7 @@ static hipError_t alloc_golden(riros_golden g, const uint64_t* stimulus, hipStre
     hipError_t e = hipMalloc((void**)&g->G, gbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&g->Gn, gbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&g->Bp, bpbytes);
+    if (e == hipSuccess && d->img.max_width <= 32) e = hipMalloc((void**)&g->Gn32, gbytes / 2);
     if (e == hipSuccess) e = hipMalloc((void**)&g->stim, sbytes);
     if (e == hipSuccess && d->img.npi > 0)
         e = hipMemcpyAsync(g->stim, stimulus, (size_t)T * d->img.npi * sizeof(uint64_t), hipMemcpyHostToDevice, s);
@@ -272,7 +276,7 @@ int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void*
     g->T = T;
     hipError_t e = alloc_golden(g, stimulus, s);
     if (e == hipSuccess) e = riros::launch_golden(d->dev, g->stim, T, g->G, s);
-    if (e == hipSuccess) e = riros::launch_golden_layouts(d->dev, g->G, T, g->Gn, g->Bp, s);
+    if (e == hipSuccess) e = riros::launch_golden_layouts(d->dev, g->G, T, g->Gn, g->Bp, g->Gn32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         free_golden_mem(g);
@@ -318,7 +322,7 @@ int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_
     if (e == hipSuccess) e = hipMemcpyAsync(djobs.p, jobs.data(), n * sizeof(riros::GoldenJob), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = riros::launch_golden_many(n, dtd.p, djobs.p, s);
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i)
-        e = riros::launch_golden_layouts(designs[i]->dev, gs[i]->G, T[i], gs[i]->Gn, gs[i]->Bp, s);
+        e = riros::launch_golden_layouts(designs[i]->dev, gs[i]->G, T[i], gs[i]->Gn, gs[i]->Bp, gs[i]->Gn32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         for (riros_golden g : gs)
@@ -530,7 +534,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.unified = opts->unified;
         p.share = opts->struct_share;
         p.heavy_wg = opts->heavy_wg > 0 ? opts->heavy_wg : 64;
-        p.w32 = im.max_width <= 32;
+        p.w32 = im.max_width <= 32 && g->Gn32 != nullptr;   // 32-bit lanes read the 32-bit trace
         p.lockstep = opts->lockstep ? 1 : 0;
         p.deal = (uint32_t)opts->deal;
         p.head_lanes = (uint32_t)opts->head_lanes;
@@ -752,6 +756,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
     uint32_t Nmax = 0, Lmax = 0, Rmax = 0, Tmax = 0, Wmax = 0;
+    bool all_gn32 = true;
     for (uint32_t i = 0; i < n; ++i) {
         if (!designs[i] || !goldens[i] || goldens[i]->d != designs[i])
             return set_err(RIROS_EINVAL, "design " + std::to_string(i) + ": missing or mismatched golden trace");
@@ -769,6 +774,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
         Rmax = std::max(Rmax, im.R);
         Tmax = std::max(Tmax, goldens[i]->T);
         Wmax = std::max(Wmax, im.max_width);
+        all_gn32 = all_gn32 && goldens[i]->Gn32 != nullptr;
     }
     if (total >= 0xFFFFFFFFull) return set_err(RIROS_EINVAL, "too many faults");
     const size_t lds = riros::wave_lds_words(Nmax, Lmax, Rmax, riros::kWordsNarrow) * sizeof(uint32_t);
@@ -881,7 +887,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.unified = opts->unified;
     p.share = opts->struct_share;
     p.heavy_wg = opts->heavy_wg > 0 ? (uint32_t)opts->heavy_wg : 64u;
-    p.w32 = Wmax <= 32;
+    p.w32 = Wmax <= 32 && all_gn32;   // 32-bit lanes read every design's 32-bit trace
     p.lockstep = opts->lockstep ? 1 : 0;
     p.deal = (uint32_t)opts->deal;
     p.head_lanes = (uint32_t)opts->head_lanes;
@@ -899,7 +905,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
             le = riros::launch_golden_many(n, d_td, d_jobs, b->cap_stream);
             for (uint32_t i = 0; i < n && le == hipSuccess; ++i)
                 le = riros::launch_golden_layouts(designs[i]->dev, goldens[i]->G, goldens[i]->T, goldens[i]->Gn,
-                                                  goldens[i]->Bp, b->cap_stream);
+                                                  goldens[i]->Bp, goldens[i]->Gn32, b->cap_stream);
         }
         if (le == hipSuccess) le = riros::launch_twod_batch(p, b->tw, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);

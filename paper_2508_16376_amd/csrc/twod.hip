@@ -121,14 +121,14 @@ __device__ __forceinline__ uint32_t pick4(uint32_t k, uint32_t a, uint32_t b, ui
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
 }
 
-// A node's golden value in cycle t from the node-major trace: the whole word,
-// or (32-bit lanes, every node at most 32 bits wide) its low half, one
-// 4-byte load.
+// A node's golden value in cycle t from the node-major trace: the 64-bit
+// word, or (32-bit lanes, every node at most 32 bits wide) the 32-bit copy,
+// whose lines hold twice the cycles.
 template <typename V>
-__device__ __forceinline__ V gold_at(const uint64_t* __restrict__ Gn, size_t i)
+__device__ __forceinline__ V gold_at(const uint64_t* __restrict__ Gn, const uint32_t* __restrict__ Gn32, size_t i)
 {
     if constexpr (sizeof(V) == 8) return Gn[i];
-    else return reinterpret_cast<const uint32_t*>(Gn)[2 * i];
+    else return Gn32[i];
 }
 
 // The operator table on 32-bit words (every operand and result at most 32
@@ -183,11 +183,12 @@ struct LaneDesign {
     const uint64_t* Gn;
     const uint64_t* Bp;
     uint32_t T, TW;
+    const uint32_t* Gn32;
 };
 
 __device__ __forceinline__ LaneDesign lane_design(const DevDesign& d, const GoldenView& g)
 {
-    return LaneDesign{d.u2i, d.lrec, d.fo, d.rfo, d.bp_off, g.Gn, g.Bp, g.T, g.TW};
+    return LaneDesign{d.u2i, d.lrec, d.fo, d.rfo, d.bp_off, g.Gn, g.Bp, g.T, g.TW, g.Gn32};
 }
 
 // Where a fault's design comes from: the launch's one design, or (batched
@@ -471,12 +472,10 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
             const uint32_t m1 = n1 != kNone ? n1 : n0;
             const LaneRec r0 = d.rec[n0];
             const LaneRec r1 = d.rec[m1];
-            const V g0 = gold_at<V>(d.Gn, (size_t)n0 * T + t);
-            const V g1 = gold_at<V>(d.Gn, (size_t)m1 * T + t);
-            const V x00 = gold_at<V>(d.Gn, (size_t)r0.o[0] * T + t), x01 = gold_at<V>(d.Gn, (size_t)r0.o[1] * T + t),
-                    x02 = gold_at<V>(d.Gn, (size_t)r0.o[2] * T + t);
-            const V x10 = gold_at<V>(d.Gn, (size_t)r1.o[0] * T + t), x11 = gold_at<V>(d.Gn, (size_t)r1.o[1] * T + t),
-                    x12 = gold_at<V>(d.Gn, (size_t)r1.o[2] * T + t);
+            auto gold = [&](uint32_t m) { return gold_at<V>(d.Gn, d.Gn32, (size_t)m * T + t); };
+            const V g0 = gold(n0), g1 = gold(m1);
+            const V x00 = gold(r0.o[0]), x01 = gold(r0.o[1]), x02 = gold(r0.o[2]);
+            const V x10 = gold(r1.o[0]), x11 = gold(r1.o[1]), x12 = gold(r1.o[2]);
             auto evaluate = [&](uint32_t n, const LaneRec& r, V gv, V x0, V x1, V x2) {
                 const bool comb = r.op != RIROS_OP_REG && r.op != RIROS_OP_PI && r.op != RIROS_OP_CONST;
                 V delta = 0;
