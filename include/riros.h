@@ -222,6 +222,15 @@ typedef struct {
                               heaviest) runs head_lanes to a wavefront, beside faults
                               of its own kind only, on up to 64 / head_lanes times
                               more wavefronts.  Never changes a result */
+    int32_t xcd_queues;    /* TWO_D with priorities: 1 = one light queue per XCD (the
+                              chip's 8 dies, each with its own L2): the descending
+                              order is partitioned by the fault site's XCD (blocks
+                              of 64 consecutive node ids round-robin over the 8),
+                              each part keeping its longest-first order, and a
+                              wavefront takes faults from its own XCD's part first,
+                              then from the others' once its own is empty, so faults
+                              on nearby nodes share one L2; deal is ignored.  0 = one
+                              queue.  Never changes a result */
 } riros_sim_opts;
 
 typedef struct {

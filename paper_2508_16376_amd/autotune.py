@@ -45,11 +45,12 @@ SPACE = {
     "heavy_wg": [64, 128, 256],
     "deal": [0, 8, 32],
     "head_lanes": [0, 32, 16],
+    "xcd_queues": [0, 1],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
-           "heavy_quantile": None}
+           "xcd_queues": 0, "heavy_quantile": None}
 
 
 def design_key(design, T: int, F: int, with_priority: bool) -> str:
@@ -65,7 +66,7 @@ def _opts(p, priority):
     return {"monitor_rate": p["monitor_rate"], "light_cap": p["light_cap"], "waves_per_cu": p["waves_per_cu"],
             "unified": p.get("unified", 0), "struct_share": p.get("struct_share", 0),
             "heavy_wg": p.get("heavy_wg", 0), "lockstep": p.get("lockstep", 0), "deal": p.get("deal", 0),
-            "head_lanes": p.get("head_lanes", 0), "theta": theta}
+            "head_lanes": p.get("head_lanes", 0), "xcd_queues": p.get("xcd_queues", 0), "theta": theta}
 
 
 def _time_single(d, g, faults, priority, p, reps=2):

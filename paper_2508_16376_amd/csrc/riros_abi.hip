@@ -415,11 +415,12 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
         !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg) || !valid_deal(opts->deal) ||
-        !valid_head_lanes(opts->head_lanes))
+        !valid_head_lanes(opts->head_lanes) ||
+        (opts->xcd_queues != 0 && opts->xcd_queues != 1) || (opts->lockstep != 0 && opts->lockstep != 1))
         return set_err(RIROS_EINVAL, "invalid option (waves_per_cu < 0, unified not 0 or 1, bad monitor_rate, "
                                      "light_cap not 0, 4, 8 or 16, struct_share not 0, 1, 2 or 4, heavy_wg "
-                                     "not 0, 64, 128 or 256, deal not 0, 4, 8, 16 or 32, or head_lanes not "
-                                     "in 0..64)");
+                                     "not 0, 64, 128 or 256, deal not 0, 4, 8, 16 or 32, head_lanes not "
+                                     "in 0..64, xcd_queues or lockstep not 0 or 1)");
     DeviceGuard guard(d->device);
     hipStream_t s = (hipStream_t)opts->stream;
     const bool on_dev = opts->io_on_device != 0;
@@ -538,6 +539,7 @@ int riros_fault_sim(riros_design d, riros_golden g, const riros_fault* faults, u
         p.lockstep = opts->lockstep ? 1 : 0;
         p.deal = (uint32_t)opts->deal;
         p.head_lanes = (uint32_t)opts->head_lanes;
+        p.xcd = opts->xcd_queues != 0;
         p.waves_per_cu = wpc;
         p.num_cu = d->num_cu;
         std::string err;
@@ -751,7 +753,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (opts->waves_per_cu < 0 || (opts->unified != 0 && opts->unified != 1) || !(opts->monitor_rate >= 0.f) ||
         (opts->light_cap != 0 && opts->light_cap != 4 && opts->light_cap != 8 && opts->light_cap != 16) ||
         !valid_share(opts->struct_share) || !valid_heavy_wg(opts->heavy_wg) || !valid_deal(opts->deal) ||
-        !valid_head_lanes(opts->head_lanes))
+        !valid_head_lanes(opts->head_lanes) ||
+        (opts->xcd_queues != 0 && opts->xcd_queues != 1) || (opts->lockstep != 0 && opts->lockstep != 1))
         return set_err(RIROS_EINVAL, "invalid option");
     const int dev = designs[0] ? designs[0]->device : 0;
     uint64_t total = 0;
@@ -881,7 +884,8 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.words = d_wk;
     p.cov = d_cov;
     std::string err;
-    int rc = riros::order_batch(b->tw, d_pr, d_fl, b->F, opts->theta, &p.order, b->cap_stream, err);
+    int rc = riros::order_batch(b->tw, d_pr, d_fl, b->F, opts->theta, opts->xcd_queues ? 1 : 0, &p.order,
+                                b->cap_stream, err);
     if (rc) return fail(rc, err);
     p.heavy = d_pr != nullptr && !(opts->theta > 3.0e38f);
     p.unified = opts->unified;
@@ -891,6 +895,7 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     p.lockstep = opts->lockstep ? 1 : 0;
     p.deal = (uint32_t)opts->deal;
     p.head_lanes = (uint32_t)opts->head_lanes;
+    p.xcd = opts->xcd_queues != 0;
     p.wpp = riros::words_per_pass(Nmax, Lmax, Rmax, (uint32_t)wpc);
     e = hipStreamSynchronize(b->cap_stream);
     if (e == hipSuccess) e = riros::prepare_twod_batch(p);

@@ -42,7 +42,21 @@ struct TwoDCounters {
     uint32_t inflight;                  // light faults taken by a lane and not yet finished or handed over
     uint32_t error;                     // unused (kept zero)
     alignas(128) uint32_t esc_take;     // phase-3 tickets (launch A)
+    // Per-XCD light queues (xcd mode): segment x of the light order holds the
+    // faults whose site falls to XCD x, [seg_begin[x], seg_end[x]) relative to
+    // the light part; seg_head[x] is its next position, one 128-byte line each.
+    uint32_t seg_begin[8], seg_end[8];
+    struct alignas(128) Head {
+        uint32_t v;
+    } seg_head[8];
 };
+
+// XCD of a fault's site in xcd mode: blocks of 64 consecutive node ids (a
+// template's nodes are numbered together) go round-robin to the 8 XCDs.
+__host__ __device__ __forceinline__ uint32_t site_xcd(uint32_t site)
+{
+    return (site >> 6) & 7u;
+}
 
 // Lane-private sets, held in registers: every index below is a compile-time
 // constant after unrolling, so no array leaves the register file.
@@ -216,6 +230,7 @@ struct LanePolicy {
     uint32_t deal;         // 0, or the group size g of the dealt queue head (a power of two, 4 to 32)
     uint32_t head_lanes;   // 0, or the size of a wavefront's first take, after which it takes nothing until
                            // that batch is finished
+    uint32_t xcd;          // 1: per-XCD light queues (the order was partitioned by site_xcd), 0: one queue
 };
 
 // Light-queue position p -> the queue index it takes, when the head of the
@@ -266,6 +281,13 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     // faults of their own kind only, on up to 64 / h times more wavefronts.
     // 0: first take; 1: holding the head batch; 2: refilling freely.
     uint32_t hstate = lp.head_lanes ? 0u : 2u;
+    // Per-XCD queues (xcd mode): workgroups are dispatched to the 8 XCDs
+    // round-robin, so this wavefront runs on XCD blockIdx.x % 8 and takes
+    // faults from that XCD's segment first, whose sites share that XCD's L2;
+    // when a segment runs dry it moves on to the next XCD's (stealing).
+    // cseg counts the segments this wavefront has found empty.
+    const uint32_t home = blockIdx.x & 7u;
+    uint32_t cseg = 0;
     // One design: uniform for the whole wave.  Batched: per lane, per fault.
     LaneDesign d = lane_design(src.d, src.g);
 
@@ -310,23 +332,49 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
         if (needm) {
             const uint32_t k = (uint32_t)__popcll(needm);
             const int leader = __ffsll((unsigned long long)needm) - 1;
-            uint32_t base = 0;
+            uint32_t base = 0, got = 0;
             if ((int)lane == leader) {
                 // In flight before taken (the fence waits for the increment),
                 // so that a taken fault is always counted: phase 3 ends when
                 // the queue is empty and nothing is in flight.
                 atomicAdd(&ctr->inflight, k);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                base = atomicAdd(&ctr->light_head, k);
-                const uint32_t taken = base >= nlight ? 0u : min(k, nlight - base);
+                uint32_t taken = 0;
+                if (lp.xcd) {
+                    while (cseg < 8u) {
+                        const uint32_t sg = (home + cseg) & 7u;
+                        const uint32_t len = ctr->seg_end[sg] - ctr->seg_begin[sg];
+                        const uint32_t b = atomicAdd(&ctr->seg_head[sg].v, k);
+                        if (b < len) {
+                            taken = min(k, len - b);
+                            base = ctr->seg_begin[sg] + b;
+                            if (b + k >= len) cseg++;
+                            break;
+                        }
+                        cseg++;
+                    }
+                    // light_head counts the faults taken (phase 3 ends on it).
+                    if (taken) atomicAdd(&ctr->light_head, taken);
+                } else {
+                    base = atomicAdd(&ctr->light_head, k);
+                    taken = base >= nlight ? 0u : min(k, nlight - base);
+                }
                 if (taken < k) atomicSub(&ctr->inflight, k - taken);
+                got = taken;
             }
             base = __shfl(base, leader, 64);
-            if (base + k >= nlight) exhausted = true;
+            got = __shfl(got, leader, 64);
+            if (lp.xcd) {
+                cseg = __shfl(cseg, leader, 64);
+                if (cseg >= 8u) exhausted = true;
+            } else if (base + k >= nlight) {
+                exhausted = true;
+            }
             if (need) {
-                const uint32_t idx = base + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
-                if (idx < nlight) {
-                    const uint32_t q = dealt(idx, gshift, chunks);
+                const uint32_t rank = (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
+                const uint32_t idx = base + rank;
+                if (rank < got) {
+                    const uint32_t q = lp.xcd ? idx : dealt(idx, gshift, chunks);
                     fi = lorder ? lorder[q] : q;
                     if (BATCH) {
                         const uint32_t k = src.did[fi];
@@ -784,7 +832,7 @@ __global__ void k_iota(uint32_t* __restrict__ v, uint32_t n)
 }
 
 __global__ void k_order_keys(const float* __restrict__ priority, const riros_fault* __restrict__ faults, uint32_t n,
-                             float theta, uint64_t* __restrict__ keys, uint32_t* __restrict__ idx)
+                             float theta, int xcd, uint64_t* __restrict__ keys, uint32_t* __restrict__ idx)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -792,8 +840,22 @@ __global__ void k_order_keys(const float* __restrict__ priority, const riros_fau
     uint32_t u = __float_as_uint(p);
     u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // IEEE order as unsigned order
     const uint64_t heavy = p > theta ? 1ull : 0ull;
-    keys[i] = (heavy << 63) | ((uint64_t)(u >> 19) << 32) | (uint64_t)(~faults[i].site);
+    const uint32_t site = faults[i].site;
+    const uint64_t part = xcd ? (uint64_t)site_xcd(site) << 60 : 0ull;
+    keys[i] = (heavy << 63) | part | ((uint64_t)(u >> 19) << 32) | (uint64_t)(~site);
     idx[i] = i;
+}
+
+// Segment bounds of the per-XCD light queues in a descending order whose keys
+// carry site_xcd in bits 60-62 below the heavy bit (after k_count_heavy).
+__global__ void k_seg_bounds(const uint64_t* __restrict__ sorted_desc, uint32_t n, TwoDCounters* ctr)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nh = ctr->n_heavy;
+    if (i >= n || i < nh) return;
+    const uint32_t x = (uint32_t)(sorted_desc[i] >> 60) & 7u;
+    if (i == nh || ((uint32_t)(sorted_desc[i - 1] >> 60) & 7u) != x) ctr->seg_begin[x] = i - nh;
+    if (i + 1 == n || ((uint32_t)(sorted_desc[i + 1] >> 60) & 7u) != x) ctr->seg_end[x] = i + 1 - nh;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ v, uint32_t n, uint32_t x)
@@ -830,6 +892,7 @@ __global__ void k_reset_run_counters(TwoDCounters* ctr)
         ctr->inflight = 0;
         ctr->esc_take = 0;
     }
+    if (threadIdx.x < 8) ctr->seg_head[threadIdx.x].v = 0;
 }
 
 // Coverage of each design of a campaign: workgroup k reduces faults
@@ -1052,21 +1115,23 @@ static hipError_t launch_twod_any(int cap, bool w32, const DesignSrc& src, const
 // Ordering by priority (descending) and the heavy prefix count; outside any
 // graph (the sort may use library-internal memory operations).
 static int order_by_priority(TwoDWorkspace& ws, const TwoDLayout& lay, const float* priority,
-                             const riros_fault* faults, uint32_t F, float theta, TwoDCounters* ctr, hipStream_t s,
-                             std::string& err)
+                             const riros_fault* faults, uint32_t F, float theta, int xcd, TwoDCounters* ctr,
+                             hipStream_t s, std::string& err)
 {
     char* base = (char*)ws.mem;
     uint32_t* idx = (uint32_t*)(base + lay.idx);
     uint64_t* keys_in = (uint64_t*)(base + lay.keys_in);
     uint64_t* keys_out = (uint64_t*)(base + lay.keys_out);
     uint32_t* order = (uint32_t*)(base + lay.order);
-    hipLaunchKernelGGL(k_order_keys, dim3((F + 255) / 256), dim3(256), 0, s, priority, faults, F, theta, keys_in, idx);
+    hipLaunchKernelGGL(k_order_keys, dim3((F + 255) / 256), dim3(256), 0, s, priority, faults, F, theta, xcd, keys_in,
+                       idx);
     size_t tb = lay.temp_bytes;
     hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(base + lay.temp, tb, keys_in, keys_out, idx, order,
                                                                (int)F, 0, 64, s);
     if (e != hipSuccess) { err = "priority sort failed"; return RIROS_EDEVICE; }
     if (!(theta > 3.0e38f))
         hipLaunchKernelGGL(k_count_heavy, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, ctr);
+    if (xcd) hipLaunchKernelGGL(k_seg_bounds, dim3((F + 255) / 256), dim3(256), 0, s, keys_out, F, ctr);
     return RIROS_OK;
 }
 
@@ -1107,7 +1172,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
     const uint32_t* order = nullptr;
     if (priority) {
-        rc = order_by_priority(ws, lay, priority, faults, F, p.theta, ctr, s, err);
+        rc = order_by_priority(ws, lay, priority, faults, F, p.theta, p.xcd ? 1 : 0, ctr, s, err);
         if (rc) return rc;
         order = (const uint32_t*)(base + lay.order);
     }
@@ -1117,7 +1182,7 @@ int run_twod(const DevDesign& d, TwoDWorkspace& ws, const GoldenView& gw, const 
     const uint64_t span = (uint64_t)F * gw.T + 1;
     const bool heavy = priority != nullptr && !(p.theta > 3.0e38f);
     hipError_t e = launch_twod_any<false>(p.light_cap, p.w32, src, mx, faults, F, order, heavy, p.unified, p.share,
-                                          (uint32_t)p.heavy_wg, LanePolicy{p.lockstep, p.deal, p.head_lanes}, ctr,
+                                          (uint32_t)p.heavy_wg, LanePolicy{p.lockstep, p.deal, p.head_lanes, p.xcd && priority ? 1u : 0u}, ctr,
                                           esc, drop, heavy_ws, span,
                                           blocks,
                                           rate_num,
@@ -1152,7 +1217,7 @@ hipError_t prepare_twod_batch(BatchPlan& b)
     return e;
 }
 
-int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta,
+int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta, int xcd,
                 const uint32_t** order, hipStream_t s, std::string& err)
 {
     TwoDLayout lay;
@@ -1163,7 +1228,7 @@ int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* fau
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, ctr);
     *order = nullptr;
     if (priority) {
-        rc = order_by_priority(ws, lay, priority, faults, F, theta, ctr, s, err);
+        rc = order_by_priority(ws, lay, priority, faults, F, theta, xcd, ctr, s, err);
         if (rc) return rc;
         *order = (const uint32_t*)(base + lay.order);
     }
@@ -1184,7 +1249,7 @@ hipError_t launch_twod_batch(const BatchPlan& b, TwoDWorkspace& ws, hipStream_t 
     hipLaunchKernelGGL((k_twod_a<CAP, true, HV, W>), dim3(b.blocks_a), dim3(HV ? b.threads_a : 64), L, s, src, mx,  \
                        b.faults, b.F, b.order,                                                                   \
                        ctr, esc, b.drop, b.ws, b.rate_num, b.unified, b.heavy_wg > 64 ? 1 : 0,                       \
-                       LanePolicy{b.lockstep, b.deal, b.head_lanes},                                             \
+                       LanePolicy{b.lockstep, b.deal, b.head_lanes, b.xcd && b.order ? 1u : 0u},                                             \
                        b.detect,                                                                                  \
                        b.events,                                                                                  \
                        b.words)

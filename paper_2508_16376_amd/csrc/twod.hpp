@@ -28,6 +28,7 @@ struct TwoDParams {
     int lockstep = 0;           // light lanes of a wavefront start their cycles together
     uint32_t deal = 0;          // light queue dealt in groups of this many faults (0 = queue order)
     uint32_t head_lanes = 0;    // a wavefront's first take, finished before it takes more (0 = off)
+    bool xcd = false;           // per-XCD light queues (with priorities)
     int waves_per_cu = 0;
     int num_cu = 0;
     float monitor_rate = 0.f;   // hand a light fault over above this many events per cycle (0 = never)
@@ -71,6 +72,7 @@ struct BatchPlan {
     int lockstep = 0;         // light lanes of a wavefront start their cycles together
     uint32_t deal = 0;        // light queue dealt in groups of this many faults (0 = queue order)
     uint32_t head_lanes = 0;  // a wavefront's first take, finished before it takes more (0 = off)
+    bool xcd = false;         // per-XCD light queues (with priorities; the order was partitioned at creation)
     int drop = 1;
     int light_cap = 8;
     uint32_t rate_num = 0;
@@ -91,7 +93,7 @@ hipError_t prepare_twod_batch(BatchPlan& b);
 // Order the concatenated faults by priority (NULL: keep them in order), faults
 // of one site together within a priority band; sets the heavy prefix.  Not
 // capturable.
-int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta,
+int order_batch(TwoDWorkspace& ws, const float* priority, const riros_fault* faults, uint32_t F, float theta, int xcd,
                 const uint32_t** order, hipStream_t s, std::string& err);
 // The capturable part of a campaign run: counter reset, launches A and B,
 // stamp advance, per-design coverage.  ws must have been prepared by order_batch.

@@ -55,7 +55,7 @@ class SimOpts(ctypes.Structure):
                 ("struct_share", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("words", ctypes.c_void_p), ("campaign_golden", ctypes.c_int32),
                 ("heavy_wg", ctypes.c_int32), ("lockstep", ctypes.c_int32), ("deal", ctypes.c_int32),
-                ("head_lanes", ctypes.c_int32)]
+                ("head_lanes", ctypes.c_int32), ("xcd_queues", ctypes.c_int32)]
 
 
 class TrainCfg(ctypes.Structure):
@@ -255,16 +255,17 @@ COVERAGE_FIELDS = 5
 
 def make_opts(mode=MODE_PLAIN, drop=True, io_on_device=False, waves_per_cu=0, priority=None,
               theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0, stream=None, struct_share=0,
-              words=None, campaign_golden=False, heavy_wg=0, lockstep=0, deal=0, head_lanes=0) -> SimOpts:
+              words=None, campaign_golden=False, heavy_wg=0, lockstep=0, deal=0, head_lanes=0,
+              xcd_queues=0) -> SimOpts:
     return SimOpts(mode, 1 if drop else 0, 1 if io_on_device else 0, waves_per_cu, _ptr(priority),
                    theta, light_cap, unified, monitor_rate, struct_share, _stream_ptr(stream), _ptr(words),
-                   1 if campaign_golden else 0, heavy_wg, 1 if lockstep else 0, deal, head_lanes)
+                   1 if campaign_golden else 0, heavy_wg, int(lockstep), deal, head_lanes, int(xcd_queues))
 
 
 def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_PLAIN, drop=True,
               waves_per_cu=0, priority=None, theta=math.inf, light_cap=0, unified=0, monitor_rate=0.0,
               stream=None, with_events=True, struct_share=0, words_out=None, heavy_wg=0, lockstep=0, deal=0,
-              head_lanes=0):
+              head_lanes=0, xcd_queues=0):
     """riros_fault_sim on host arrays: returns (detect, events, coverage dict).
     words_out (optional uint64[F]) receives the per-fault byte-model words."""
     fl = np.ascontiguousarray(faults)
@@ -276,7 +277,7 @@ def fault_sim(design: Design, golden: Golden, faults: np.ndarray, *, mode=MODE_P
         assert words_out.dtype == np.uint64 and words_out.size == F and words_out.flags.c_contiguous
     opts = make_opts(mode, drop, False, waves_per_cu, pr, theta, light_cap, unified, monitor_rate, stream,
                      struct_share, words_out, heavy_wg=heavy_wg, lockstep=lockstep, deal=deal,
-                     head_lanes=head_lanes)
+                     head_lanes=head_lanes, xcd_queues=xcd_queues)
     cov = Coverage()
     _check(lib().riros_fault_sim(design.handle, golden.handle, _ptr(fl), F, ctypes.byref(opts), _ptr(detect),
                                  _ptr(events), ctypes.byref(cov)))
@@ -365,7 +366,7 @@ class Batch:
 
     def __init__(self, designs, goldens, fault_lists, priorities=None, *, drop=True, waves_per_cu=0,
                  theta=math.inf, light_cap=0, monitor_rate=0.0, unified=0, struct_share=0, campaign_golden=False,
-                 heavy_wg=0, lockstep=0, deal=0, head_lanes=0):
+                 heavy_wg=0, lockstep=0, deal=0, head_lanes=0, xcd_queues=0):
         n = len(designs)
         fls = [np.ascontiguousarray(f) for f in fault_lists]
         self.F = [int(f.size) for f in fls]
@@ -381,7 +382,7 @@ class Batch:
             pp = (ctypes.c_void_p * n)(*[0 if p is None else p.ctypes.data for p in prs])
         opts = make_opts(MODE_TWO_D, drop, False, waves_per_cu, None, theta, light_cap, unified, monitor_rate, None,
                          struct_share, campaign_golden=campaign_golden, heavy_wg=heavy_wg, lockstep=lockstep,
-                         deal=deal, head_lanes=head_lanes)
+                         deal=deal, head_lanes=head_lanes, xcd_queues=xcd_queues)
         h = ctypes.c_void_p()
         _check(lib().riros_batch_create(n, dh, gh, fp, _ptr(Fa), pp, ctypes.byref(opts), ctypes.byref(h)))
         del keep

@@ -13,13 +13,14 @@ def test_descent_finds_the_coordinatewise_minimum():
         c += 0 if p["heavy_wg"] == 128 else 0.125
         c += 0 if p["deal"] == 8 else 0.0625
         c += 0 if p["head_lanes"] == 16 else 0.03125
+        c += 0 if p["xcd_queues"] == 1 else 0.015625
         return c
 
     t = autotune.Autotuner()
     best, bt = t._descend(cost, with_priority=True)
     assert best == {"unified": 0, "monitor_rate": 4.0, "light_cap": 4, "waves_per_cu": 16, "struct_share": 1,
                     "heavy_wg": 128, "lockstep": 1, "deal": 8, "head_lanes": 16,
-                    "heavy_quantile": 0.99}
+                    "xcd_queues": 1, "heavy_quantile": 0.99}
     assert bt == 0
     # every candidate is a point of the space; the descent times no point
     # twice, and then the three fastest points are timed twice more each

@@ -125,7 +125,8 @@ def test_campaign_golden_in_graph_on_every_replay(small_campaign):
 def test_campaign_of_narrow_template_designs():
     """A campaign whose designs are all at most 32 bits wide (template designs:
     light lanes keep 32-bit values) with priorities, a heavy prefix on
-    two-wavefront workgroups and the unified schedule, on two replays."""
+    two-wavefront workgroups, the unified schedule, per-XCD light queues and
+    lanes in lockstep, on two replays."""
     ws = []
     for k in range(4):
         s = 626262 + 1000 * k
@@ -136,7 +137,8 @@ def test_campaign_of_narrow_template_designs():
     ds, gs = _load(ws)
     prios = [np.log2(1 + r[1].astype(np.float32)) for r in refs]
     b = riros.Batch(ds, gs, [w.faults for w in ws], prios, theta=float(np.quantile(np.concatenate(prios), 0.95)),
-                    monitor_rate=2.0, unified=1, struct_share=2, heavy_wg=128, light_cap=4)
+                    monitor_rate=2.0, unified=1, struct_share=2, heavy_wg=128, light_cap=4, xcd_queues=1,
+                    lockstep=1)
     for rep in range(2):
         b.launch()
         for i in range(len(ws)):

@@ -331,6 +331,26 @@ def test_two_d_head_batch(small, tiny, head_lanes):
     _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, True, head_lanes=head_lanes)
 
 
+@pytest.mark.parametrize("light_cap", [4, 8])
+def test_two_d_xcd_queues(small, tiny, light_cap):
+    """Per-XCD light queues: the priority order partitioned by the site's XCD,
+    each wavefront taking its own XCD's part first and then the others'; with
+    a heavy prefix, lockstep, a head batch, one and twelve wavefronts per
+    compute unit, drop on and off; without priorities the option changes
+    nothing."""
+    prio = (W.counter_values(37, 0, small.faults.size) >> np.uint64(50)).astype(np.float32)
+    for drop in (True, False):
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, xcd_queues=1,
+               waves_per_cu=1, light_cap=light_cap, lockstep=1, priority=prio, unified=1, struct_share=4)
+        _check(small.design, small.stimulus, small.T, small.faults, riros.MODE_TWO_D, drop, xcd_queues=1,
+               waves_per_cu=12, light_cap=light_cap, monitor_rate=2.0, priority=prio,
+               theta=float(np.quantile(prio, 0.95)), head_lanes=16)
+    _check(small.design, small.stimulus, small.T, small.faults[:700], riros.MODE_TWO_D, True, xcd_queues=1,
+           light_cap=light_cap)
+    _check(tiny.design, tiny.stimulus, tiny.T, tiny.faults, riros.MODE_TWO_D, True, xcd_queues=1,
+           priority=np.ones(tiny.faults.size, np.float32), light_cap=light_cap)
+
+
 def test_two_d_dealt_medium_full_size():
     """50,000 faults over 256 wavefronts: 16,384 dealt positions, then the rest
     of the queue in order."""
@@ -350,7 +370,8 @@ def test_two_d_rejects_bad_options(tiny):
     g = riros.Golden(d, tiny.stimulus, tiny.T)
     for kw in ({"unified": 2}, {"monitor_rate": -1.0}, {"light_cap": 5}, {"struct_share": 3}, {"struct_share": 8},
                {"heavy_wg": 96}, {"heavy_wg": 512}, {"deal": 2}, {"deal": 12}, {"deal": 64},
-               {"head_lanes": -1}, {"head_lanes": 65}):
+               {"head_lanes": -1}, {"head_lanes": 65}, {"xcd_queues": 2},
+               {"lockstep": 2}):
         with pytest.raises(riros.RirosError):
             riros.fault_sim(d, g, tiny.faults[:10], mode=riros.MODE_TWO_D, **kw)
 
