@@ -113,15 +113,19 @@ void riros_free_design(riros_design d);
  * trace is kept in three layouts (cycle-major, node-major and one bit-plane
  * per node bit), about 16*T*num_nodes + T*sum(widths)/8 bytes of device
  * memory, plus 4*T*num_nodes for a 32-bit node-major copy when no node is
- * wider than 32 bits.  Errors: RIROS_EINVAL
+ * wider than 32 bits.  A design whose non-input nodes fall into independent
+ * components of at most 4,096 nodes (with the inputs and constants they
+ * read) runs by parts, one workgroup per part with the part's values in LDS;
+ * otherwise one workgroup walks the whole design.  Errors: RIROS_EINVAL
  * (T == 0, NULL pointers), RIROS_ENOMEM, RIROS_EDEVICE.  *out is a new handle. */
 int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream,
                      riros_golden* out);
 void riros_free_golden(riros_golden g);
 
-/* riros_golden_sim for n designs at once: one kernel launch simulates every
- * design's fault-free machine, one workgroup per design (the designs are
- * independent), then each trace gets its other layouts.  stimulus[i] and T[i]
+/* riros_golden_sim for n designs at once: one kernel launch simulates the
+ * fault-free machines of every design in fewer than two parts, one workgroup
+ * per design (the designs are independent), a second one the parts of the
+ * others, one workgroup per part; then each trace gets its other layouts.  stimulus[i] and T[i]
  * as for riros_golden_sim; out[i] receives design i's handle.  Errors as for
  * riros_golden_sim (nothing is returned on failure). */
 int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_t* const* stimulus,

@@ -266,6 +266,164 @@ int build_image(const riros_design_desc& d, Image& img, std::string& err)
     return RIROS_OK;
 }
 
+// Golden-machine parts: union-find over the non-source nodes, components
+// packed longest first into the emptiest part (LPT), then each part's local
+// program in level order.
+bool build_golden_parts(const Image& img, uint32_t max_parts, GoldenParts& gp)
+{
+    gp = GoldenParts{};
+    const uint32_t N = img.N;
+    auto source = [&](uint32_t n) { return img.desc[n].op == RIROS_OP_PI || img.desc[n].op == RIROS_OP_CONST; };
+    std::vector<uint32_t> up(N);
+    for (uint32_t i = 0; i < N; ++i) up[i] = i;
+    auto find = [&](uint32_t x) {
+        while (up[x] != x) {
+            up[x] = up[up[x]];
+            x = up[x];
+        }
+        return x;
+    };
+    auto operands = [&](uint32_t n, uint32_t* ops) -> uint32_t {
+        const Desc& d = img.desc[n];
+        if (d.op == RIROS_OP_REG) {
+            ops[0] = d.a;
+            return 1;
+        }
+        if (!op_is_comb(d.op)) return 0;
+        const uint32_t k = (uint32_t)op_arity(d.op);
+        ops[0] = d.a;
+        if (k > 1) ops[1] = d.b;
+        if (k > 2) ops[2] = d.c;
+        return k;
+    };
+    for (uint32_t n = 0; n < N; ++n) {
+        if (source(n)) continue;
+        uint32_t ops[3];
+        const uint32_t k = operands(n, ops);
+        for (uint32_t j = 0; j < k; ++j)
+            if (!source(ops[j])) {
+                const uint32_t a = find(n), b = find(ops[j]);
+                if (a != b) up[a] = b;
+            }
+    }
+    // Components: their nodes and the sources they read.
+    std::vector<uint32_t> comp_of(N, kNoGid);
+    std::vector<std::vector<uint32_t>> members;
+    for (uint32_t n = 0; n < N; ++n) {
+        if (source(n)) continue;
+        const uint32_t r = find(n);
+        if (comp_of[r] == kNoGid) {
+            comp_of[r] = (uint32_t)members.size();
+            members.emplace_back();
+        }
+        members[comp_of[r]].push_back(n);
+    }
+    const uint32_t C = (uint32_t)members.size();
+    std::vector<uint32_t> csize(C);
+    for (uint32_t c = 0; c < C; ++c) {
+        std::vector<uint32_t> src;
+        for (uint32_t n : members[c]) {
+            uint32_t ops[3];
+            const uint32_t k = operands(n, ops);
+            for (uint32_t j = 0; j < k; ++j)
+                if (source(ops[j])) src.push_back(ops[j]);
+        }
+        std::sort(src.begin(), src.end());
+        src.erase(std::unique(src.begin(), src.end()), src.end());
+        csize[c] = (uint32_t)(members[c].size() + src.size());
+        if (csize[c] > kGoldenPartCap) return false;
+    }
+    if (C == 0) return false;
+    // LPT packing; more parts while one exceeds the cap (sources shared by
+    // components of a part are counted once there, so the sum bounds it).
+    std::vector<uint32_t> order(C);
+    for (uint32_t c = 0; c < C; ++c) order[c] = c;
+    std::sort(order.begin(), order.end(),
+              [&](uint32_t x, uint32_t y) { return csize[x] > csize[y] || (csize[x] == csize[y] && x < y); });
+    uint32_t P = std::max<uint32_t>(1, std::min(C, max_parts));
+    std::vector<uint32_t> part_of(C);
+    for (;;) {
+        std::vector<uint64_t> load(P, 0);
+        bool fits = true;
+        for (uint32_t c : order) {
+            uint32_t best = 0;
+            for (uint32_t p = 1; p < P; ++p)
+                if (load[p] < load[best]) best = p;
+            part_of[c] = best;
+            load[best] += csize[c];
+            if (load[best] > kGoldenPartCap) fits = false;
+        }
+        if (fits) break;
+        if (P >= C) return false;
+        P = std::min(C, P * 2);
+    }
+    // Local programs.  Owned sources: a source belongs to the first part that
+    // reads it; sources nobody reads belong to part 0.
+    std::vector<std::vector<uint32_t>> parts(P);
+    for (uint32_t c = 0; c < C; ++c)
+        for (uint32_t n : members[c]) parts[part_of[c]].push_back(n);
+    std::vector<uint8_t> owned_src(N, 0);
+    std::vector<uint32_t> loc(N, kNoGid);
+    gp.part_off.push_back(0);
+    gp.lvl_off.push_back(0);
+    for (uint32_t p = 0; p < P; ++p) {
+        std::vector<uint32_t> nodes = parts[p];
+        std::vector<uint32_t> src;
+        for (uint32_t n : parts[p]) {
+            uint32_t ops[3];
+            const uint32_t k = operands(n, ops);
+            for (uint32_t j = 0; j < k; ++j)
+                if (source(ops[j])) src.push_back(ops[j]);
+        }
+        if (p == 0) {
+            std::vector<uint8_t> read(N, 0);
+            for (uint32_t n = 0; n < N; ++n) {
+                if (source(n)) continue;
+                uint32_t ops[3];
+                const uint32_t k = operands(n, ops);
+                for (uint32_t j = 0; j < k; ++j) read[ops[j]] = 1;
+            }
+            for (uint32_t n = 0; n < N; ++n)
+                if (source(n) && !read[n]) src.push_back(n);
+        }
+        std::sort(src.begin(), src.end());
+        src.erase(std::unique(src.begin(), src.end()), src.end());
+        nodes.insert(nodes.end(), src.begin(), src.end());
+        std::sort(nodes.begin(), nodes.end(), [&](uint32_t x, uint32_t y) {
+            return img.level[x] < img.level[y] || (img.level[x] == img.level[y] && x < y);
+        });
+        for (uint32_t i = 0; i < nodes.size(); ++i) loc[nodes[i]] = i;
+        uint32_t prev_level = 0xFFFFFFFFu;
+        for (uint32_t i = 0; i < nodes.size(); ++i) {
+            const uint32_t n = nodes[i];
+            const Desc& d = img.desc[n];
+            GNode g{d.op, d.width, 0, 0, d.a, d.b, d.c, n};
+            if (source(n)) {
+                if (owned_src[n]) g.gid = kNoGid;
+                owned_src[n] = 1;
+            } else if (d.op == RIROS_OP_REG) {
+                g.a = loc[d.a];
+            } else {
+                const uint32_t k = (uint32_t)op_arity(d.op);
+                g.a = loc[d.a];
+                if (k > 1) g.b = loc[d.b];
+                if (k > 2) g.c = loc[d.c];
+            }
+            if (img.level[n] != prev_level) {
+                gp.lvl.push_back(i);
+                prev_level = img.level[n];
+            }
+            gp.node.push_back(g);
+        }
+        gp.lvl.push_back((uint32_t)nodes.size());
+        for (uint32_t n : nodes) loc[n] = kNoGid;
+        gp.part_off.push_back((uint32_t)gp.node.size());
+        gp.lvl_off.push_back((uint32_t)gp.lvl.size());
+        gp.max_nodes = std::max<uint32_t>(gp.max_nodes, (uint32_t)nodes.size());
+    }
+    return true;
+}
+
 // Predictor graph features.  The cone of a node is the number of distinct
 // nodes reached through combinational users, registers fed counted but not
 // crossed, the node itself excluded, capped at kConeCap.  Register depth is a

@@ -78,6 +78,36 @@ struct Image {
     uint32_t max_width = 0;                     // widest node
 };
 
+// Independent parts of a design for the golden machine.  The non-source
+// nodes (not inputs or constants) fall into connected components (a register
+// joined to its D input, an operator to its operands); components are packed
+// into parts of at most kGoldenPartCap local nodes, each part with copies of
+// the inputs and constants it reads, so that one workgroup can simulate a
+// part for every cycle with its values in LDS and no other part's values.
+// A local node is the design's descriptor with its operand ids (operands of
+// an operator, the D input of a register) replaced by local indexes; gid is
+// the internal id whose trace column the part writes, or kNoGid for a copied
+// source another part owns.
+constexpr uint32_t kGoldenPartCap = 4096;
+constexpr uint32_t kNoGid = 0xFFFFFFFFu;
+struct GNode {
+    uint8_t op, width, pad0, pad1;
+    uint32_t a, b, c;
+    uint32_t gid;
+};
+static_assert(sizeof(GNode) == 20, "golden part node layout");
+struct GoldenParts {
+    std::vector<GNode> node;          // every part's local nodes, part after part, in level order
+    std::vector<uint32_t> part_off;   // P+1 offsets into node
+    std::vector<uint32_t> lvl;        // per part, the local offsets where its levels start, and its size
+    std::vector<uint32_t> lvl_off;    // P+1 offsets into lvl
+    uint32_t max_nodes = 0;           // largest part
+};
+
+// Fills gp and returns true when every component fits a part; false (gp
+// empty) when a component is larger, the design then runs on one workgroup.
+bool build_golden_parts(const Image& img, uint32_t max_parts, GoldenParts& gp);
+
 // Per-node graph features of the load predictor (internal numbering):
 // log2(1 + forward cone, capped), level / deepest level, fewest registers to
 // an output (capped, -1 when none), log2(width).

@@ -57,16 +57,50 @@ struct __attribute__((aligned(16))) Slot {
 
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s);
 
+// A design's golden parts on the device (build_golden_parts); P = 0 when the
+// design has none (it then runs on one workgroup).
+struct DevGoldenParts {
+    const GNode* node;
+    const uint32_t* part_off;
+    const uint32_t* lvl;
+    const uint32_t* lvl_off;
+    uint32_t P, max_nodes;
+};
+
+// Golden trace by parts: one workgroup per part, the part's values of the
+// current and the previous cycle in LDS.  golden_parts_setup (once, outside
+// any graph capture) allows the kernel the LDS of the largest part.
+hipError_t golden_parts_setup();
+
+// One part of one design's golden machine, for launches that run the parts
+// of many designs at once.
+struct GPartJob {
+    const GNode* node;
+    const uint32_t* part_off;
+    const uint32_t* lvl;
+    const uint32_t* lvl_off;
+    const uint64_t* stim;
+    uint64_t* G;
+    uint32_t part, npi, N, T;
+};
+
+// n part jobs in one launch, one workgroup each (jobs: a device table);
+// max_nodes: the largest of their parts.
+hipError_t launch_golden_parts_many(uint32_t n, const GPartJob* jobs, uint32_t max_nodes, hipStream_t s);
+hipError_t launch_golden_parts(const DevDesign& d, const DevGoldenParts& gp, const uint64_t* stim, uint32_t T,
+                               uint64_t* G, hipStream_t s);
+
 // One design's golden run of a batched launch: its device stimulus [T][npi],
 // cycle count and row-major trace.
 struct GoldenJob {
     const uint64_t* stim;
     uint64_t* G;
     uint32_t T;
+    uint32_t design;   // index into the launch's design table
 };
 
-// n designs' golden traces in one launch, one workgroup per design (td, jobs:
-// device tables of n entries).
+// n golden traces in one launch, one workgroup per job (jobs: a device table
+// of n entries; td: the design table their indexes refer to).
 hipError_t launch_golden_many(uint32_t n, const DevDesign* td, const GoldenJob* jobs, hipStream_t s);
 
 struct PlainWorkspace {

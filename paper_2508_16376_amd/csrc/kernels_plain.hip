@@ -56,7 +56,7 @@ __global__ __launch_bounds__(1024) void k_golden_many(const DevDesign* __restric
                                                       const GoldenJob* __restrict__ jobs)
 {
     const GoldenJob j = jobs[blockIdx.x];
-    golden_design(td[blockIdx.x], j.stim, j.T, j.G);
+    golden_design(td[j.design], j.stim, j.T, j.G);
 }
 
 hipError_t launch_golden(const DevDesign& d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s)
@@ -69,6 +69,96 @@ hipError_t launch_golden_many(uint32_t n, const DevDesign* td, const GoldenJob* 
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_golden_many, dim3(n), dim3(1024), 0, s, td, jobs);
+    return hipGetLastError();
+}
+
+// Golden machine by parts: workgroup p simulates part p (independent of every
+// other part: its components read only each other and the inputs and
+// constants copied into it) for every cycle.  The part's values of the current
+// cycle (cur) and the previous one (prev, which registers read) stay in LDS;
+// each level's nodes are spread over the workgroup's lanes, a barrier between
+// levels; at the end of a cycle the part writes the trace columns it owns.
+__device__ void golden_part(const GPartJob& j, uint32_t max_nodes)
+{
+    extern __shared__ uint64_t gpv[];
+    const uint32_t o = j.part_off[j.part], m = j.part_off[j.part + 1] - o;
+    const uint32_t l0 = j.lvl_off[j.part], l1 = j.lvl_off[j.part + 1];
+    const GNode* __restrict__ nd = j.node + o;
+    const uint64_t* __restrict__ stim = j.stim;
+    uint64_t* __restrict__ G = j.G;
+    const uint32_t T = j.T, npi = j.npi;
+    uint64_t* cur = gpv;
+    uint64_t* prev = gpv + max_nodes;
+    const size_t N = j.N;
+    for (uint32_t t = 0; t < T; ++t) {
+        for (uint32_t li = l0; li + 1 < l1; ++li) {
+            const uint32_t lo = j.lvl[li], hi = j.lvl[li + 1];
+            for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+                const GNode x = nd[i];
+                uint64_t v;
+                switch (x.op) {
+                case RIROS_OP_CONST: v = make_u64(x.a, x.b); break;
+                case RIROS_OP_PI: v = stim[(size_t)t * npi + x.a] & width_mask(x.width); break;
+                case RIROS_OP_REG: v = t == 0 ? make_u64(x.b, x.c) : prev[x.a]; break;
+                default: {
+                    const int ar = dev_arity(x.op);
+                    const uint64_t x0 = cur[x.a];
+                    const uint64_t x1 = ar >= 2 ? cur[x.b] : 0;
+                    const uint64_t x2 = ar >= 3 ? cur[x.c] : 0;
+                    v = apply_opw(x.op, x.width, x.b, x.c, x0, x1, x2);
+                }
+                }
+                cur[i] = v;
+            }
+            __syncthreads();
+        }
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint32_t gid = nd[i].gid;
+            if (gid != kNoGid) G[(size_t)t * N + gid] = cur[i];
+        }
+        uint64_t* tmp = cur;
+        cur = prev;
+        prev = tmp;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_golden_parts(DevDesign d, DevGoldenParts gp,
+                                                      const uint64_t* __restrict__ stim, uint32_t T,
+                                                      uint64_t* __restrict__ G)
+{
+    const GPartJob j{gp.node, gp.part_off, gp.lvl, gp.lvl_off, stim, G, blockIdx.x, d.npi, d.N, T};
+    golden_part(j, gp.max_nodes);
+}
+
+// Workgroup k: part jobs[k] (parts of many designs in one launch).
+__global__ __launch_bounds__(256) void k_golden_parts_many(const GPartJob* __restrict__ jobs, uint32_t max_nodes)
+{
+    golden_part(jobs[blockIdx.x], max_nodes);
+}
+
+hipError_t golden_parts_setup()
+{
+    const int lds = (int)(2 * kGoldenPartCap * sizeof(uint64_t));
+    hipError_t e = hipFuncSetAttribute((const void*)k_golden_parts, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_golden_parts_many, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+}
+
+hipError_t launch_golden_parts(const DevDesign& d, const DevGoldenParts& gp, const uint64_t* stim, uint32_t T,
+                               uint64_t* G, hipStream_t s)
+{
+    const size_t lds = (size_t)2 * gp.max_nodes * sizeof(uint64_t);
+    hipLaunchKernelGGL(k_golden_parts, dim3(gp.P), dim3(256), lds, s, d, gp, stim, T, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_golden_parts_many(uint32_t n, const GPartJob* jobs, uint32_t max_nodes, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_golden_parts_many, dim3(n), dim3(256), (size_t)2 * max_nodes * sizeof(uint64_t), s, jobs,
+                       max_nodes);
     return hipGetLastError();
 }
 

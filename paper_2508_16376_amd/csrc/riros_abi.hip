@@ -115,6 +115,8 @@ struct riros_design_s {
     uint64_t* stamp_dev = nullptr;   // slot stamps above this are unused (advanced on the device by every run)
     uint64_t* ws_words = nullptr;    // per-fault byte-model words when the caller asks for none (grow-only)
     size_t ws_words_cap = 0;
+    // golden machine by parts (P = 0: one workgroup for the whole design)
+    riros::DevGoldenParts gparts{};
     // two-dimensional kernel workspace
     riros::TwoDWorkspace twod{};
     // concurrent (node-major) mode workspace
@@ -232,6 +234,30 @@ int riros_load_design(const riros_design_desc* desc, riros_design* out)
         }
     d->dev = riros::DevDesign{p_desc, p_lvl, p_level, p_fo_off, p_fo, p_fo_lvl, p_rfo_off, p_rfo, p_u2i, p_uw,
                               p_rec, p_lrec, p_fopk, p_bp, im.N, im.L, im.R, im.npi, im.bp_rows};
+    {
+        riros::GoldenParts gp;
+        if (riros::build_golden_parts(im, 4u * (uint32_t)std::max(1, d->num_cu), gp)) {
+            riros::GNode* p_gn = nullptr;
+            uint32_t *p_po = nullptr, *p_gl = nullptr, *p_glo = nullptr;
+            hipError_t ge[4] = {dev_upload(&p_gn, gp.node), dev_upload(&p_po, gp.part_off), dev_upload(&p_gl, gp.lvl),
+                                dev_upload(&p_glo, gp.lvl_off)};
+            for (void* p : {(void*)p_gn, (void*)p_po, (void*)p_gl, (void*)p_glo})
+                if (p) d->owned.push_back(p);
+            for (hipError_t x : ge)
+                if (x != hipSuccess) {
+                    free_design_mem(d);
+                    delete d;
+                    return hip_err(x, "design upload");
+                }
+            d->gparts = riros::DevGoldenParts{p_gn, p_po, p_gl, p_glo, (uint32_t)gp.part_off.size() - 1, gp.max_nodes};
+            e = riros::golden_parts_setup();
+            if (e != hipSuccess) {
+                free_design_mem(d);
+                delete d;
+                return hip_err(e, "golden parts setup");
+            }
+        }
+    }
     e = hipMalloc((void**)&d->d_cov, sizeof(riros_coverage));
     if (e == hipSuccess) e = hipMalloc((void**)&d->d_bad, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&d->stamp_dev, sizeof(uint64_t));
@@ -263,6 +289,23 @@ int riros_design_info(riros_design d, uint32_t* num_nodes, uint32_t* num_levels,
     return RIROS_OK;
 }
 
+// The part jobs of one design's golden machine (for launches of many designs).
+static void append_part_jobs(riros_design d, const uint64_t* stim, uint32_t T, uint64_t* G,
+                             std::vector<riros::GPartJob>& jobs, uint32_t& max_nodes)
+{
+    const riros::DevGoldenParts& gp = d->gparts;
+    for (uint32_t p = 0; p < gp.P; ++p)
+        jobs.push_back(riros::GPartJob{gp.node, gp.part_off, gp.lvl, gp.lvl_off, stim, G, p, d->img.npi, d->img.N, T});
+    max_nodes = std::max(max_nodes, gp.max_nodes);
+}
+
+// The golden machine of one design: by parts when it has them.
+static hipError_t golden_run(riros_design d, const uint64_t* stim, uint32_t T, uint64_t* G, hipStream_t s)
+{
+    return d->gparts.P ? riros::launch_golden_parts(d->dev, d->gparts, stim, T, G, s)
+                       : riros::launch_golden(d->dev, stim, T, G, s);
+}
+
 int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void* stream, riros_golden* out)
 {
     if (!d || !out) return set_err(RIROS_EINVAL, "NULL argument");
@@ -275,7 +318,7 @@ int riros_golden_sim(riros_design d, const uint64_t* stimulus, uint32_t T, void*
     g->d = d;
     g->T = T;
     hipError_t e = alloc_golden(g, stimulus, s);
-    if (e == hipSuccess) e = riros::launch_golden(d->dev, g->stim, T, g->G, s);
+    if (e == hipSuccess) e = golden_run(d, g->stim, T, g->G, s);
     if (e == hipSuccess) e = riros::launch_golden_layouts(d->dev, g->G, T, g->Gn, g->Bp, g->Gn32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -303,7 +346,13 @@ int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_
     hipStream_t s = (hipStream_t)stream;
     std::vector<riros_golden> gs(n, nullptr);
     std::vector<riros::DevDesign> td(n);
-    std::vector<riros::GoldenJob> jobs(n);
+    // Designs in fewer than two parts run one workgroup each in one launch (so
+    // they run at the same time); the parts of the others one workgroup each,
+    // in a second launch.
+    std::vector<riros::GoldenJob> jobs;
+    std::vector<riros::GPartJob> pjobs;
+    uint32_t pmax = 0;
+    DevBuf<riros::GPartJob> dpjobs;
     DevBuf<riros::DevDesign> dtd;
     DevBuf<riros::GoldenJob> djobs;
     hipError_t e = hipSuccess;
@@ -314,13 +363,22 @@ int riros_golden_sim_many(uint32_t n, const riros_design* designs, const uint64_
         gs[i]->T = T[i];
         e = alloc_golden(gs[i], stimulus[i], s);
         td[i] = designs[i]->dev;
-        jobs[i] = riros::GoldenJob{gs[i]->stim, gs[i]->G, T[i]};
+        if (designs[i]->gparts.P < 2) jobs.push_back(riros::GoldenJob{gs[i]->stim, gs[i]->G, T[i], i});
+        else append_part_jobs(designs[i], gs[i]->stim, T[i], gs[i]->G, pjobs, pmax);
     }
-    if (e == hipSuccess) e = dtd.alloc(n);
-    if (e == hipSuccess) e = djobs.alloc(n);
-    if (e == hipSuccess) e = hipMemcpyAsync(dtd.p, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(djobs.p, jobs.data(), n * sizeof(riros::GoldenJob), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = riros::launch_golden_many(n, dtd.p, djobs.p, s);
+    const uint32_t npj = (uint32_t)pjobs.size();
+    if (e == hipSuccess && npj) e = dpjobs.alloc(npj);
+    if (e == hipSuccess && npj)
+        e = hipMemcpyAsync(dpjobs.p, pjobs.data(), npj * sizeof(riros::GPartJob), hipMemcpyHostToDevice, s);
+    const uint32_t nj = (uint32_t)jobs.size();
+    if (e == hipSuccess && nj) e = dtd.alloc(n);
+    if (e == hipSuccess && nj) e = djobs.alloc(nj);
+    if (e == hipSuccess && nj)
+        e = hipMemcpyAsync(dtd.p, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nj)
+        e = hipMemcpyAsync(djobs.p, jobs.data(), nj * sizeof(riros::GoldenJob), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = riros::launch_golden_many(nj, dtd.p, djobs.p, s);
+    if (e == hipSuccess) e = riros::launch_golden_parts_many(npj, dpjobs.p, pmax, s);
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i)
         e = riros::launch_golden_layouts(designs[i]->dev, gs[i]->G, T[i], gs[i]->Gn, gs[i]->Bp, gs[i]->Gn32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -848,10 +906,27 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? RIROS_ENOMEM : RIROS_EDEVICE, "campaign allocation");
     A(hipMemcpy(d_td, td.data(), n * sizeof(riros::DevDesign), hipMemcpyHostToDevice));
     A(hipMemcpy(d_tg, tg.data(), n * sizeof(riros::GoldenView), hipMemcpyHostToDevice));
+    // Golden machines in the graph: designs in fewer than two parts one
+    // workgroup each (one launch, all of them at once), the parts of the
+    // others one workgroup each (a second launch).
+    uint32_t n_jobs = 0, n_pjobs = 0, pmax = 0;
+    riros::GPartJob* d_pjobs = nullptr;
     if (d_jobs) {
-        std::vector<riros::GoldenJob> jobs(n);
-        for (uint32_t i = 0; i < n; ++i) jobs[i] = riros::GoldenJob{goldens[i]->stim, goldens[i]->G, goldens[i]->T};
-        A(hipMemcpy(d_jobs, jobs.data(), n * sizeof(riros::GoldenJob), hipMemcpyHostToDevice));
+        std::vector<riros::GoldenJob> jobs;
+        std::vector<riros::GPartJob> pjobs;
+        for (uint32_t i = 0; i < n; ++i) {
+            if (designs[i]->gparts.P < 2)
+                jobs.push_back(riros::GoldenJob{goldens[i]->stim, goldens[i]->G, goldens[i]->T, i});
+            else
+                append_part_jobs(designs[i], goldens[i]->stim, goldens[i]->T, goldens[i]->G, pjobs, pmax);
+        }
+        n_jobs = (uint32_t)jobs.size();
+        n_pjobs = (uint32_t)pjobs.size();
+        if (n_jobs) A(hipMemcpy(d_jobs, jobs.data(), n_jobs * sizeof(riros::GoldenJob), hipMemcpyHostToDevice));
+        if (n_pjobs) {
+            A(batch_alloc(b, &d_pjobs, n_pjobs));
+            A(hipMemcpy(d_pjobs, pjobs.data(), n_pjobs * sizeof(riros::GPartJob), hipMemcpyHostToDevice));
+        }
     }
     if (b->F) {
         A(hipMemcpy(d_fl, fl.data(), fl.size() * sizeof(riros_fault), hipMemcpyHostToDevice));
@@ -905,9 +980,12 @@ int riros_batch_create(uint32_t n, const riros_design* designs, const riros_gold
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         if (d_jobs) {
-            // The golden machines of all designs (one workgroup each), then
-            // each trace's other layouts, then the fault simulation.
-            le = riros::launch_golden_many(n, d_td, d_jobs, b->cap_stream);
+            // The golden machines of all designs (one workgroup for each
+            // design without parts, one launch by parts for each of the
+            // others), then each trace's other layouts, then the fault
+            // simulation.
+            le = riros::launch_golden_many(n_jobs, d_td, d_jobs, b->cap_stream);
+            if (le == hipSuccess) le = riros::launch_golden_parts_many(n_pjobs, d_pjobs, pmax, b->cap_stream);
             for (uint32_t i = 0; i < n && le == hipSuccess; ++i)
                 le = riros::launch_golden_layouts(designs[i]->dev, goldens[i]->G, goldens[i]->T, goldens[i]->Gn,
                                                   goldens[i]->Bp, goldens[i]->Gn32, b->cap_stream);

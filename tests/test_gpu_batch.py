@@ -122,6 +122,37 @@ def test_campaign_golden_in_graph_on_every_replay(small_campaign):
     b.close()
 
 
+def test_golden_many_and_in_graph_mixing_parts_and_whole_designs():
+    """A campaign whose designs take both golden paths: template designs (by
+    parts) and a layered design too large for one part (one workgroup for the
+    whole design).  riros_golden_sim_many and the golden recomputed inside the
+    campaign graph both give the oracle's traces and results."""
+    import torch
+    ws = []
+    for k in range(3):
+        s = 737373 + 1000 * k
+        d = W.gen_templates(s, n_nodes=1200 + 900 * k, name=f"tmpl{k}")
+        T = 150 + 50 * k
+        ws.append(W.Workload(d.name, d, W.gen_stimulus(s, d, T), W.gen_faults(s, d, 800), T))
+    ws.append(W.medium(seed=838383, F=600, T=100, n_nodes=5200))
+    refs = [oracle.fault_sim(w.design, w.stimulus, w.T, w.faults) for w in ws]
+    ds = [riros.Design(w.design) for w in ws]
+    gs = riros.Golden.many(ds, [w.stimulus for w in ws], [w.T for w in ws])
+    for w, g in zip(ws, gs):
+        np.testing.assert_array_equal(g.read(), oracle.golden(w.design, w.stimulus, w.T), err_msg=w.name)
+    b = riros.Batch(ds, gs, [w.faults for w in ws], None, unified=1, campaign_golden=True)
+    for rep in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        for i, w in enumerate(ws):
+            det, ev, _ = b.read(i)
+            np.testing.assert_array_equal(det, refs[i][0], err_msg=f"replay {rep} design {i}")
+            np.testing.assert_array_equal(ev, refs[i][1], err_msg=f"replay {rep} design {i}")
+        for w, g in zip(ws, gs):
+            np.testing.assert_array_equal(g.read(), oracle.golden(w.design, w.stimulus, w.T), err_msg=w.name)
+    b.close()
+
+
 def test_campaign_of_narrow_template_designs():
     """A campaign whose designs are all at most 32 bits wide (template designs:
     light lanes keep 32-bit values) with priorities, a heavy prefix on

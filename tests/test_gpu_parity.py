@@ -58,6 +58,26 @@ def test_golden_matches_oracle(tiny, small):
         np.testing.assert_array_equal(g.read(), oracle.golden(w.design, w.stimulus, w.T))
 
 
+def test_golden_by_parts_and_whole_design():
+    """Golden traces of a template design (its components packed into
+    hundreds of parts, one workgroup each, values in LDS), of a layered
+    design with one component larger than a part (one workgroup for the whole
+    design), and of the heavy-tailed design (100,000 nodes in 1,024 parts)
+    against the oracle's, every node and cycle."""
+    cases = []
+    d = W.gen_templates(515151, n_nodes=3000, name="tmpl")
+    cases.append((d, W.gen_stimulus(515151, d, 300), 300))
+    w = W.medium(seed=919, F=10, T=120, n_nodes=6000)
+    cases.append((w.design, w.stimulus, w.T))
+    w = W.heavy_tailed()
+    cases.append((w.design, w.stimulus, 64))
+    for design, stim, T in cases:
+        print(f"[golden] {design.name} N={design.num_nodes} T={T}", flush=True)
+        dd = riros.Design(design)
+        g = riros.Golden(dd, stim, T)
+        np.testing.assert_array_equal(g.read(), oracle.golden(design, stim, T), err_msg=design.name)
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("drop", [True, False])
 def test_tiny_full(tiny, mode, drop):
