@@ -358,10 +358,27 @@ bool build_golden_parts(const Image& img, uint32_t max_parts, GoldenParts& gp)
         P = std::min(C, P * 2);
     }
     // Local programs.  Owned sources: a source belongs to the first part that
-    // reads it; sources nobody reads belong to part 0.
+    // reads it; sources nobody reads go to parts of their own (at most
+    // kGoldenPartCap each) after the others.
     std::vector<std::vector<uint32_t>> parts(P);
     for (uint32_t c = 0; c < C; ++c)
         for (uint32_t n : members[c]) parts[part_of[c]].push_back(n);
+    {
+        std::vector<uint8_t> read(N, 0);
+        for (uint32_t n = 0; n < N; ++n) {
+            if (source(n)) continue;
+            uint32_t ops[3];
+            const uint32_t k = operands(n, ops);
+            for (uint32_t j = 0; j < k; ++j) read[ops[j]] = 1;
+        }
+        std::vector<uint32_t> unread;
+        for (uint32_t n = 0; n < N; ++n)
+            if (source(n) && !read[n]) unread.push_back(n);
+        for (size_t i = 0; i < unread.size(); i += kGoldenPartCap)
+            parts.emplace_back(unread.begin() + i,
+                               unread.begin() + std::min(unread.size(), (size_t)i + kGoldenPartCap));
+        P = (uint32_t)parts.size();
+    }
     std::vector<uint8_t> owned_src(N, 0);
     std::vector<uint32_t> loc(N, kNoGid);
     gp.part_off.push_back(0);
@@ -374,17 +391,6 @@ bool build_golden_parts(const Image& img, uint32_t max_parts, GoldenParts& gp)
             const uint32_t k = operands(n, ops);
             for (uint32_t j = 0; j < k; ++j)
                 if (source(ops[j])) src.push_back(ops[j]);
-        }
-        if (p == 0) {
-            std::vector<uint8_t> read(N, 0);
-            for (uint32_t n = 0; n < N; ++n) {
-                if (source(n)) continue;
-                uint32_t ops[3];
-                const uint32_t k = operands(n, ops);
-                for (uint32_t j = 0; j < k; ++j) read[ops[j]] = 1;
-            }
-            for (uint32_t n = 0; n < N; ++n)
-                if (source(n) && !read[n]) src.push_back(n);
         }
         std::sort(src.begin(), src.end());
         src.erase(std::unique(src.begin(), src.end()), src.end());
