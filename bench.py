@@ -452,7 +452,8 @@ def main():
     log(f"[bench] autotuner: {params} in {tune_s:.2f}s")
 
     # The ablation ladder: static order all light; a static heuristic (the
-    # site's cone size) under the same heavy rule as the network; the network.
+    # site's cone size) under the same heavy rule as the network, then with the
+    # workgroup-wide heavy split; the network.
     ladder = {}
     static = None
     if multi:
@@ -472,6 +473,13 @@ def main():
                 ladder["static_cone_heuristic"] = {"fault_cycles_per_s": rate(heur),
                                                    "kernel_ms": heur["kernel_ms"],
                                                    "identical": bool(same_results(heur, plain))}
+                # The same static order with the workgroup-wide heavy split:
+                # the top 1% by cone size start on four-wavefront structural
+                # workgroups (the ladder's "+ heavy split" step).
+                split = dict(params, heavy_quantile=0.99, heavy_wg=256, struct_share=4)
+                hs = job.run(riros.MODE_TWO_D, psteps, 1, autotune.single_kwargs(split, cone))
+                ladder["static_cone_heavy_wg_split"] = {"fault_cycles_per_s": rate(hs), "kernel_ms": hs["kernel_ms"],
+                                                        "identical": bool(same_results(hs, plain))}
         job.set_priority(preds)
         best = job.run(riros.MODE_TWO_D, args.steps, args.warmup, autotune.single_kwargs(params, preds))
     if static:
