@@ -308,10 +308,11 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
     bool finished = false;   // this lane finished or handed over a fault in the last iteration
     // Lanes with 32-bit values and capacity 4 evaluate two nodes per
     // iteration (see below) and keep the record of the last register they
-    // evaluated (creg, not the site): when that register is the first
-    // divergent one of the next cycle, as a latent accumulator's is in every
-    // cycle, it is evaluated at the cycle start without a load, and its users
-    // go into the same iteration's pair.  Wider values or larger sets leave
+    // evaluated (creg): when that register is the first divergent one of the
+    // next cycle, as a latent accumulator's is in every cycle, it is
+    // evaluated at the cycle start without loading its record (only its
+    // golden word when it is the fault site), and its users go into the same
+    // iteration's pair.  Wider values or larger sets leave
     // no registers for either.
     constexpr bool kPair = sizeof(V) == 4 && C <= 4;
     uint32_t creg = kNone;
@@ -478,16 +479,25 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 if (!site_reg && !pend.insert(site)) esc_now = true;
                 if (kPair && !esc_now && creg != kNone && rcur.id[0] == creg) {
                     // A register's evaluation: its delta is its staged next
-                    // state (an event with a divergent input and output).
+                    // state (an event with a divergent input), and when the
+                    // register is the site, that state with the fault
+                    // applied to it (which may mask it).
+                    V delta = rcur.dx[0];
+                    if (creg == site) {
+                        const V gv = gold_at<V>(d.Gn, d.Gn32, (size_t)creg * d.T + t);
+                        delta = apply_fault_v<V>(gv ^ delta, fbit, fval, t, ft0) ^ gv;
+                    }
                     ev++;
                     wk += 2u * crec.words;
-                    on_divergent(creg, rcur.dx[0], crec);
+                    if (delta != 0) on_divergent(creg, delta, crec);
                     rk = 1;
                 }
             }
             in_cycle = true;
         }
-        if (!evaluated && !esc_now) {
+        // The cycle-start evaluation of the site's own register can leave
+        // nothing to evaluate (no other divergent register, nothing pending).
+        if (!evaluated && !esc_now && (rk < rcur.n || pend.n > 0)) {
             // Evaluate the next node (registers of the cycle first, then the
             // lowest pending node: users always have larger ids) and, in the
             // same iteration, the node after it, when that one is still the
@@ -530,7 +540,7 @@ __device__ void light_phase(const DesignSrc& src, const riros_fault* __restrict_
                 bool din = false;
                 if (r.op == RIROS_OP_REG) {
                     delta = rcur.find(n, din);
-                    if (kPair && n != site) {
+                    if (kPair) {
                         creg = n;
                         crec = r;
                     }

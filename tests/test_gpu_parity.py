@@ -371,6 +371,26 @@ def test_two_d_xcd_queues(small, tiny, light_cap):
            priority=np.ones(tiny.faults.size, np.float32), light_cap=light_cap)
 
 
+@pytest.mark.parametrize("drop", [True, False])
+def test_two_d_32bit_lanes_template_design(drop):
+    """A template design (every node at most 32 bits wide: the light lanes
+    keep 32-bit values, evaluate two nodes per iteration and cache the
+    register they last evaluated, also when it is the fault site), all of its
+    faults and flips, under several schedules."""
+    d = W.gen_templates(252525, n_nodes=4000, name="tmpl32")
+    T = 400
+    stim = W.gen_stimulus(252525, d, T)
+    fl = W.gen_faults(252525, d, 6000)
+    flips = W.gen_flip_faults(252526, d, 1500, T)
+    prio = (W.counter_values(41, 0, fl.size) >> np.uint64(50)).astype(np.float32)
+    for kw in ({"light_cap": 4, "lockstep": 1, "priority": prio},
+               {"light_cap": 4, "lockstep": 0, "unified": 1, "struct_share": 4, "priority": prio},
+               {"light_cap": 4, "lockstep": 1, "waves_per_cu": 1},
+               {"light_cap": 8, "lockstep": 1, "priority": prio, "monitor_rate": 2.0}):
+        _check(d, stim, T, fl, riros.MODE_TWO_D, drop, **kw)
+    _check(d, stim, T, flips, riros.MODE_TWO_D, drop, light_cap=4, lockstep=1)
+
+
 def test_two_d_dealt_medium_full_size():
     """50,000 faults over 256 wavefronts: 16,384 dealt positions, then the rest
     of the queue in order."""
