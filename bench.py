@@ -556,7 +556,9 @@ def main():
         "two_d_predictor": ladder["two_d_predictor"],
         "speedup_vs_plain": None if plain is None else value / rate(plain),
         "autotuned": {"params": params, "tune_s": tune_s, "budget_s": TUNE_BUDGET_S,
-                      "sample_faults": min(total_faults, TUNE_SAMPLE) if not multi else total_faults},
+                      "sample_faults": min(total_faults, TUNE_SAMPLE) if not multi else total_faults,
+                      "whole_list_params": list(autotune.SCALE_PARAMS)
+                      if not multi and total_faults > TUNE_SAMPLE else []},
         "predictor": pred_info,
         "no_drop": nodrop,
         "concurrent": conc,

@@ -48,6 +48,8 @@ SPACE = {
     "xcd_queues": [0, 1],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
+# Parameters whose best value depends on how many faults are in flight.
+SCALE_PARAMS = ("waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified")
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
            "xcd_queues": 0, "heavy_quantile": None}
@@ -101,13 +103,15 @@ class Autotuner:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1, sort_keys=True)
 
-    def _descend(self, measure, with_priority: bool, confirm: int = 3):
+    def _descend(self, measure, with_priority: bool, confirm: int = 3, start=None, names=None):
+        """Coordinate descent from ``start`` (default DEFAULT) over the
+        parameters in ``names`` (default every one of SPACE)."""
         t_start = time.perf_counter()
 
         def spent():
             return self.budget_s is not None and time.perf_counter() - t_start > self.budget_s
 
-        best = dict(DEFAULT)
+        best = dict(DEFAULT if start is None else start)
         best_t = measure(best)
         self.log.append({"params": dict(best), "ms": best_t})
         timed = [(best_t, dict(best))]
@@ -118,7 +122,7 @@ class Autotuner:
         for _ in range(2):
             start = dict(best)
             for name, values in SPACE.items():
-                if name == "heavy_quantile" and not with_priority:
+                if (name == "heavy_quantile" and not with_priority) or (names is not None and name not in names):
                     continue
                 for v in values:
                     cand = dict(best)
@@ -157,11 +161,23 @@ class Autotuner:
             key += f"-s{len(sample)}"
         if key in self.cache:
             return self.cache[key]["params"]
+        full_ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
+        full = faults
         if sample is not None:
             faults = np.ascontiguousarray(faults[sample])
             priority = None if priority is None else priority[sample]
         ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
         best, t = self._descend(lambda p: _time_single(d, g, faults, ps, p), priority is not None)
+        if sample is not None:
+            # Occupancy, workspace sharing, the structural workgroup size and
+            # lockstep trade against contention, which grows with the number
+            # of faults in flight: a sample holding a fraction of the list
+            # favours fewer resident wavefronts than the whole list does.
+            # They are descended again on the whole list from the sample's
+            # best point; the monitor, capacity and ordering keep the
+            # sample's choice.
+            best, t = self._descend(lambda p: _time_single(d, g, full, full_ps, p), priority is not None,
+                                    start=best, names=SCALE_PARAMS)
         self.cache[key] = {"params": best, "ms": t}
         self._save()
         return best

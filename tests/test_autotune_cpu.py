@@ -1,4 +1,6 @@
 """Host logic of the autotuner: coordinate descent over the schedule space."""
+import numpy as np
+
 from paper_2508_16376_amd import autotune
 
 
@@ -85,3 +87,31 @@ def test_budget_stops_the_descent_and_keeps_the_best_so_far():
     distinct = len({tuple(sorted(c.items(), key=lambda kv: kv[0])) for c in calls})
     assert distinct <= 5
     assert best["monitor_rate"] in (1.0, 2.0)
+
+
+def test_sampled_tuning_redoes_the_scale_parameters_on_the_whole_list(monkeypatch):
+    """With a sample, the monitor and capacity keep the sample's choice, and
+    occupancy is descended again on the whole list, where the sample's best
+    occupancy is not the whole list's."""
+    from paper_2508_16376_amd import workloads as W
+    d = W.gen_templates(5, n_nodes=300, name="t")
+    faults = W.gen_faults(5, d, 400)
+    sample = np.arange(0, 400, 4)
+    sizes = []
+
+    def fake_time(dd, g, fl, ps, p):
+        sizes.append(fl.size)
+        t = 10.0 if p["monitor_rate"] == 0.0 else 20.0
+        t += 0.5 if p["light_cap"] == 4 else 1.0
+        best_wpc = 8 if fl.size == sample.size else 16
+        return t + (0.0 if p["waves_per_cu"] == best_wpc else 2.0)
+
+    monkeypatch.setattr(autotune, "_time_single", fake_time)
+    t = autotune.Autotuner()
+    best = t.tune_single(d, None, None, faults, priority=None, T=10, sample=sample)
+    assert best["monitor_rate"] == 0.0 and best["light_cap"] == 4
+    assert best["waves_per_cu"] == 16
+    assert sample.size in sizes and faults.size in sizes
+    # The whole list only times the scale parameters: the monitor, capacity
+    # and queue options stay at the sample's choice in every point timed there.
+    assert sizes.index(faults.size) > 0 and all(s == faults.size for s in sizes[sizes.index(faults.size):])
