@@ -44,12 +44,13 @@ SPACE = {
     "struct_share": [1, 2, 4],
     "heavy_wg": [64, 128, 256],
     "deal": [0, 8, 32],
-    "head_lanes": [0, 32, 16],
+    "head_lanes": [0, 32, 16, 64],
     "xcd_queues": [0, 1],
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
-# Parameters whose best value depends on how many faults are in flight.
-SCALE_PARAMS = ("waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified")
+# Parameters whose best value depends on how many faults are in flight (or,
+# for the head batch, how many heavy faults there are to spread).
+SCALE_PARAMS = ("waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified", "head_lanes")
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
            "xcd_queues": 0, "heavy_quantile": None}
@@ -172,7 +173,9 @@ class Autotuner:
             # Occupancy, workspace sharing, the structural workgroup size and
             # lockstep trade against contention, which grows with the number
             # of faults in flight: a sample holding a fraction of the list
-            # favours fewer resident wavefronts than the whole list does.
+            # favours fewer resident wavefronts than the whole list does.  The
+            # head batch's size decides how the heavy faults, a fixed share
+            # of the list, spread over the wavefronts.
             # They are descended again on the whole list from the sample's
             # best point; the monitor, capacity and ordering keep the
             # sample's choice.
