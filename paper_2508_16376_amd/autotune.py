@@ -72,14 +72,14 @@ def _opts(p, priority):
             "head_lanes": p.get("head_lanes", 0), "xcd_queues": p.get("xcd_queues", 0), "theta": theta}
 
 
-def _time_single(d, g, faults, priority, p, reps=2):
+def _time_single(d, g, faults, priority, p, reps=2, drop=True):
     """Best of ``reps`` timed runs after one untimed run (the first launch of a
     kernel instance pays for loading its code object)."""
     kw = _opts(p, priority)
-    riros.fault_sim(d, g, faults, mode=riros.MODE_TWO_D, priority=priority, with_events=False, **kw)
+    riros.fault_sim(d, g, faults, mode=riros.MODE_TWO_D, drop=drop, priority=priority, with_events=False, **kw)
     best = math.inf
     for _ in range(reps):
-        riros.fault_sim(d, g, faults, mode=riros.MODE_TWO_D, priority=priority, with_events=False, **kw)
+        riros.fault_sim(d, g, faults, mode=riros.MODE_TWO_D, drop=drop, priority=priority, with_events=False, **kw)
         best = min(best, riros.last_kernel_ms())
     return best
 
@@ -154,12 +154,20 @@ class Autotuner:
             _, best_t, best = min(scored, key=lambda x: x[0])
         return best, best_t
 
-    def tune_single(self, design_np, d, g, faults, priority=None, T=None, sample=None):
+    def tune_single(self, design_np, d, g, faults, priority=None, T=None, sample=None, drop=True, start=None,
+                    names=None):
         """Parameters for riros_fault_sim(mode=TWO_D) on this design and fault
-        list.  sample: time the candidates on these fault indexes only."""
+        list.  sample: time the candidates on these fault indexes only.  drop:
+        the detect-and-drop convention the parameters are for.  start, names:
+        descend from ``start`` over these parameters only (default: from
+        DEFAULT over every one)."""
         key = design_key(design_np, T or 0, faults.size, priority is not None)
         if sample is not None:
             key += f"-s{len(sample)}"
+        if not drop:
+            key += "-nodrop"
+        if names is not None:
+            key += "-" + "-".join(names)
         if key in self.cache:
             return self.cache[key]["params"]
         full_ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
@@ -168,8 +176,9 @@ class Autotuner:
             faults = np.ascontiguousarray(faults[sample])
             priority = None if priority is None else priority[sample]
         ps = None if priority is None else np.ascontiguousarray(priority, dtype=np.float32)
-        best, t = self._descend(lambda p: _time_single(d, g, faults, ps, p), priority is not None)
-        if sample is not None:
+        best, t = self._descend(lambda p: _time_single(d, g, faults, ps, p, drop=drop), priority is not None,
+                                start=start, names=names)
+        if sample is not None and names is None:
             # Occupancy, workspace sharing, the structural workgroup size and
             # lockstep trade against contention, which grows with the number
             # of faults in flight: a sample holding a fraction of the list
@@ -179,7 +188,7 @@ class Autotuner:
             # They are descended again on the whole list from the sample's
             # best point; the monitor, capacity and ordering keep the
             # sample's choice.
-            best, t = self._descend(lambda p: _time_single(d, g, full, full_ps, p), priority is not None,
+            best, t = self._descend(lambda p: _time_single(d, g, full, full_ps, p, drop=drop), priority is not None,
                                     start=best, names=SCALE_PARAMS)
         self.cache[key] = {"params": best, "ms": t}
         self._save()

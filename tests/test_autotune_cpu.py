@@ -99,7 +99,7 @@ def test_sampled_tuning_redoes_the_scale_parameters_on_the_whole_list(monkeypatc
     sample = np.arange(0, 400, 4)
     sizes = []
 
-    def fake_time(dd, g, fl, ps, p):
+    def fake_time(dd, g, fl, ps, p, drop=True):
         sizes.append(fl.size)
         t = 10.0 if p["monitor_rate"] == 0.0 else 20.0
         t += 0.5 if p["light_cap"] == 4 else 1.0
@@ -115,3 +115,27 @@ def test_sampled_tuning_redoes_the_scale_parameters_on_the_whole_list(monkeypatc
     # The whole list only times the scale parameters: the monitor, capacity
     # and queue options stay at the sample's choice in every point timed there.
     assert sizes.index(faults.size) > 0 and all(s == faults.size for s in sizes[sizes.index(faults.size):])
+
+
+def test_no_drop_tuning_descends_only_the_named_parameters(monkeypatch):
+    """A descent restricted to some parameters, for the no-dropping
+    convention, starts from the given point, times every candidate without
+    dropping and changes nothing else."""
+    from paper_2508_16376_amd import workloads as W
+    d = W.gen_templates(6, n_nodes=300, name="t")
+    faults = W.gen_faults(6, d, 300)
+    seen = []
+
+    def fake_time(dd, g, fl, ps, p, drop=True):
+        seen.append((dict(p), drop))
+        return (0.0 if p["light_cap"] == 8 else 1.0) + (0.0 if p["monitor_rate"] == 0.0 else 0.5)
+
+    monkeypatch.setattr(autotune, "_time_single", fake_time)
+    start = dict(autotune.DEFAULT, light_cap=4, monitor_rate=4.0, waves_per_cu=16, head_lanes=64)
+    best = autotune.Autotuner().tune_single(d, None, None, faults, T=10, drop=False, start=start,
+                                            names=("light_cap", "monitor_rate", "unified"))
+    assert best["light_cap"] == 8 and best["monitor_rate"] == 0.0
+    assert all(not dr for _, dr in seen)
+    for p, _ in seen:
+        assert {k: v for k, v in p.items() if k not in ("light_cap", "monitor_rate", "unified")} == \
+            {k: v for k, v in start.items() if k not in ("light_cap", "monitor_rate", "unified")}
