@@ -391,6 +391,24 @@ def test_two_d_32bit_lanes_template_design(drop):
     _check(d, stim, T, flips, riros.MODE_TWO_D, drop, light_cap=4, lockstep=1)
 
 
+@pytest.mark.parametrize("drop", [True, False])
+def test_two_d_tuned_schedules_template_design(drop):
+    """The schedules the autotuner picks on the template workloads: head
+    batches filling all 64 lanes, free-running lanes, the unified schedule
+    with the monitor off and workspaces shared by four wavefronts, and
+    (without dropping) capacity 8; every fault against the oracle."""
+    d = W.gen_templates(262626, n_nodes=6000, name="tmpl_tuned")
+    T = 600
+    stim = W.gen_stimulus(262626, d, T)
+    fl = W.gen_faults(262626, d, 8000)
+    prio = (W.counter_values(43, 0, fl.size) >> np.uint64(50)).astype(np.float32)
+    base = {"lockstep": 0, "head_lanes": 64, "waves_per_cu": 16, "heavy_wg": 64, "priority": prio}
+    for kw in ({"light_cap": 4, "unified": 0, "monitor_rate": 4.0, "struct_share": 2},
+               {"light_cap": 4, "unified": 1, "monitor_rate": 0.0, "struct_share": 4},
+               {"light_cap": 8, "unified": 1, "monitor_rate": 0.0, "struct_share": 4}):
+        _check(d, stim, T, fl, riros.MODE_TWO_D, drop, **base, **kw)
+
+
 def test_two_d_dealt_medium_full_size():
     """50,000 faults over 256 wavefronts: 16,384 dealt positions, then the rest
     of the queue in order."""
