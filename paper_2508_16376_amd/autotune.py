@@ -49,8 +49,10 @@ SPACE = {
     "heavy_quantile": [None, 0.99, 0.9, 0.6, 0.0],
 }
 # Parameters whose best value depends on how many faults are in flight (or,
-# for the head batch, how many heavy faults there are to spread).
-SCALE_PARAMS = ("waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified", "head_lanes")
+# for the head batch, how many heavy faults there are to spread; for the
+# monitor, how many faults reach the structural path, which pays together
+# with the unified schedule or not at all).
+SCALE_PARAMS = ("monitor_rate", "waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified", "head_lanes")
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
            "xcd_queues": 0, "heavy_quantile": None}
@@ -184,10 +186,11 @@ class Autotuner:
             # of faults in flight: a sample holding a fraction of the list
             # favours fewer resident wavefronts than the whole list does.  The
             # head batch's size decides how the heavy faults, a fixed share
-            # of the list, spread over the wavefronts.
-            # They are descended again on the whole list from the sample's
-            # best point; the monitor, capacity and ordering keep the
-            # sample's choice.
+            # of the list, spread over the wavefronts, and the monitor how
+            # many faults the structural path takes, which pays only together
+            # with the unified schedule.  These are descended again on the
+            # whole list from the sample's best point; the capacity and the
+            # queue options keep the sample's choice.
             best, t = self._descend(lambda p: _time_single(d, g, full, full_ps, p, drop=drop), priority is not None,
                                     start=best, names=SCALE_PARAMS)
         self.cache[key] = {"params": best, "ms": t}

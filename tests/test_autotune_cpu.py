@@ -90,9 +90,10 @@ def test_budget_stops_the_descent_and_keeps_the_best_so_far():
 
 
 def test_sampled_tuning_redoes_the_scale_parameters_on_the_whole_list(monkeypatch):
-    """With a sample, the monitor and capacity keep the sample's choice, and
-    occupancy is descended again on the whole list, where the sample's best
-    occupancy is not the whole list's."""
+    """With a sample, the capacity keeps the sample's choice, and occupancy
+    (with the monitor and the other contention parameters) is descended again
+    on the whole list, where the sample's best occupancy is not the whole
+    list's."""
     from paper_2508_16376_amd import workloads as W
     d = W.gen_templates(5, n_nodes=300, name="t")
     faults = W.gen_faults(5, d, 400)
@@ -112,8 +113,8 @@ def test_sampled_tuning_redoes_the_scale_parameters_on_the_whole_list(monkeypatc
     assert best["monitor_rate"] == 0.0 and best["light_cap"] == 4
     assert best["waves_per_cu"] == 16
     assert sample.size in sizes and faults.size in sizes
-    # The whole list only times the scale parameters: the monitor, capacity
-    # and queue options stay at the sample's choice in every point timed there.
+    # The whole list only times the scale parameters: the capacity and the
+    # queue options stay at the sample's choice in every point timed there.
     assert sizes.index(faults.size) > 0 and all(s == faults.size for s in sizes[sizes.index(faults.size):])
 
 
