@@ -53,6 +53,14 @@ SPACE = {
 # monitor, how many faults reach the structural path, which pays together
 # with the unified schedule or not at all).
 SCALE_PARAMS = ("monitor_rate", "waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified", "head_lanes")
+# Parameters that pay only together with another's value: the unified
+# schedule needs workspaces shared by several wavefronts (one workspace per
+# wavefront holds too few of them resident), so each unified value is tried
+# with every sharing value.
+JOINT = {"unified": "struct_share"}
+# Candidate values on the whole list, where a low monitor rate hands most of
+# a million faults to the structural path and a candidate takes seconds.
+WHOLE_LIST_VALUES = {"monitor_rate": [0.0, 4.0, 8.0]}
 DEFAULT = {"unified": 1, "monitor_rate": 2.0, "light_cap": 8, "waves_per_cu": 12, "struct_share": 1,
            "heavy_wg": 64, "lockstep": 1, "deal": 0, "head_lanes": 0,
            "xcd_queues": 0, "heavy_quantile": None}
@@ -106,9 +114,12 @@ class Autotuner:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1, sort_keys=True)
 
-    def _descend(self, measure, with_priority: bool, confirm: int = 3, start=None, names=None):
+    def _descend(self, measure, with_priority: bool, confirm: int = 3, start=None, names=None, values=None):
         """Coordinate descent from ``start`` (default DEFAULT) over the
-        parameters in ``names`` (default every one of SPACE)."""
+        parameters in ``names`` (default every one of SPACE), with the
+        candidate values of ``values`` where it names a parameter (default
+        SPACE's).  A parameter of JOINT is tried with every value of its
+        partner when the partner is descended too."""
         t_start = time.perf_counter()
 
         def spent():
@@ -124,12 +135,18 @@ class Autotuner:
         # the structural path); the second pass only times unseen points.
         for _ in range(2):
             start = dict(best)
-            for name, values in SPACE.items():
+            for name, space_values in SPACE.items():
                 if (name == "heavy_quantile" and not with_priority) or (names is not None and name not in names):
                     continue
-                for v in values:
+                vals = (values or {}).get(name, space_values)
+                partner = JOINT.get(name)
+                if partner is not None and names is not None and partner not in names:
+                    partner = None
+                moves = [{name: v} for v in vals] if partner is None else \
+                    [{name: v, partner: w} for v in vals for w in (values or {}).get(partner, SPACE[partner])]
+                for mv in moves:
                     cand = dict(best)
-                    cand[name] = v
+                    cand.update(mv)
                     key = tuple(sorted(cand.items(), key=lambda kv: kv[0]))
                     if key in seen or spent():
                         continue
@@ -192,7 +209,7 @@ class Autotuner:
             # whole list from the sample's best point; the capacity and the
             # queue options keep the sample's choice.
             best, t = self._descend(lambda p: _time_single(d, g, full, full_ps, p, drop=drop), priority is not None,
-                                    start=best, names=SCALE_PARAMS)
+                                    start=best, names=SCALE_PARAMS, values=WHOLE_LIST_VALUES)
         self.cache[key] = {"params": best, "ms": t}
         self._save()
         return best

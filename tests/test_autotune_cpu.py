@@ -140,3 +140,32 @@ def test_no_drop_tuning_descends_only_the_named_parameters(monkeypatch):
     for p, _ in seen:
         assert {k: v for k, v in p.items() if k not in ("light_cap", "monitor_rate", "unified")} == \
             {k: v for k, v in start.items() if k not in ("light_cap", "monitor_rate", "unified")}
+
+
+def test_unified_is_tried_with_every_workspace_sharing():
+    """The unified schedule pays only with workspaces shared by four
+    wavefronts: a one-at-a-time descent from one workspace per wavefront
+    would never take it, the joint move does."""
+    def cost(p):
+        if p["unified"] == 1:
+            return 1.0 if p["struct_share"] == 4 else 9.0
+        return 5.0 + (0.0 if p["struct_share"] == 1 else 0.5)
+
+    start = dict(autotune.DEFAULT, unified=0, struct_share=1)
+    best, bt = autotune.Autotuner()._descend(cost, with_priority=False, start=start,
+                                             names=("unified", "struct_share"))
+    assert best["unified"] == 1 and best["struct_share"] == 4 and bt == 1.0
+
+
+def test_whole_list_values_replace_the_space():
+    """Candidate values given for the whole list replace SPACE's."""
+    timed = []
+
+    def cost(p):
+        timed.append(p["monitor_rate"])
+        return p["monitor_rate"]
+
+    start = dict(autotune.DEFAULT, monitor_rate=4.0)
+    autotune.Autotuner()._descend(cost, with_priority=False, start=start, names=("monitor_rate",),
+                                  values=autotune.WHOLE_LIST_VALUES)
+    assert set(timed) <= set(autotune.WHOLE_LIST_VALUES["monitor_rate"])
