@@ -3,18 +3,23 @@
 Chooses, per design (or campaign) and fault population, the parameters that
 decide where work runs: whether idle wavefronts take handed-over faults
 during the light launch (the unified schedule), the events-per-cycle
-threshold of the light-lane monitor, the light-lane capacity, the number of
-resident wavefronts per compute unit, how many of them share one structural
-workspace, how many wavefronts simulate one structural fault together, and
-(with a predictor) the
-predicted-load quantile above which faults start on the structural path.  The paper fixes its overload threshold
-by hand (Sec. V-A); here candidates are timed and the fastest kept, one
-parameter at a time (coordinate descent), with the result cached by design
-hash.  Candidates run on a seeded sample of the fault list (by default the
-whole list): the sample must keep more faults than the chip has lanes, or it
-would hide the contention of the structural path (one fault per wavefront)
-and pick thresholds that fail at full scale.  A wall-clock budget bounds the
-search: once it is spent the best point so far is confirmed and kept.  No
+threshold of the light-lane monitor, the light-lane capacity, whether lanes
+start their cycles in step, the number of resident wavefronts per compute
+unit, how many of them share one structural workspace, how many wavefronts
+simulate one structural fault together, how the head of the light queue
+spreads over the wavefronts (dealt out, or taken in one batch per
+wavefront), whether each XCD takes faults from its own queue, and (with a
+predictor) the predicted-load quantile above which faults start on the
+structural path.  The paper fixes its overload threshold by hand (Sec.
+V-A); here candidates are timed and the fastest kept, one parameter at a
+time (coordinate descent, with the unified schedule moved together with
+workspace sharing), with the result cached by design hash.  Candidates run
+on a seeded sample of the fault list (by default the whole list): the
+sample must keep more faults than the chip has lanes, or it would hide the
+contention of the structural path and pick thresholds that fail at full
+scale; the parameters that depend on how many faults are in flight are then
+descended again on the whole list.  A wall-clock budget bounds each
+descent: once it is spent the best point so far is confirmed and kept.  No
 parameter changes a result, only time.
 """
 from __future__ import annotations
