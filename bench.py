@@ -49,6 +49,8 @@ BYTES_PER_WORD = 4
 OPS_PER_EVENT = 10
 OPS_PER_FC = 3
 NO_DROP_SAMPLE = 20000     # faults of the no-dropping leg (seeded draw)
+NO_DROP_PROBE = 2000       # its first faults, timed first to bound the leg
+NO_DROP_MAX_MS = 3000.0    # a pass of the full sample longer than this keeps the probe, untuned
 NO_DROP_TUNE_BUDGET_S = 20.0
 NO_DROP_TUNED = ("light_cap", "monitor_rate", "unified")
 TRAIN_EPOCHS = 30
@@ -495,8 +497,27 @@ def main():
     nodrop = None
     if args.no_drop_leg != "off" and not multi:
         w = ws[0]
+        rank = np.argsort(W.counter_values(0xD0D0, 0, w.faults.size), kind="stable")
+
+        def nd_run(sel, p, runs=2):
+            pr_s = None if preds is None else np.ascontiguousarray(preds[sel], np.float32)
+            kw = autotune.single_kwargs(p, pr_s)
+            for _ in range(runs):   # the first run also loads code objects
+                det_s, ev_s, _ = riros.fault_sim(job.d, job.g, np.ascontiguousarray(w.faults[sel]),
+                                                 mode=riros.MODE_TWO_D, drop=False, priority=pr_s, **kw)
+            return det_s, ev_s, riros.last_kernel_ms()
+
+        # A design whose detected faults keep diverging across most of it
+        # every cycle (no dropping) can take seconds per thousand faults: the
+        # drop-mode schedule is timed on the sample's first faults, and when
+        # the whole sample would take too long the leg keeps those, untuned.
+        probe = np.sort(rank[:min(w.faults.size, NO_DROP_PROBE)])
+        _, _, probe_ms = nd_run(probe, params)
         n = min(w.faults.size, NO_DROP_SAMPLE)
-        idx = np.sort(np.argsort(W.counter_values(0xD0D0, 0, w.faults.size), kind="stable")[:n])
+        tune_nd = not (args.params or args.no_tune)
+        if probe_ms * n / probe.size > NO_DROP_MAX_MS:
+            n, tune_nd = probe.size, False
+        idx = np.sort(rank[:n])
         pr = None if preds is None else np.ascontiguousarray(preds[idx], np.float32)
         fl_nd = np.ascontiguousarray(w.faults[idx])
         # Without dropping, a detected fault keeps diverging for every
@@ -505,23 +526,20 @@ def main():
         # schedule are tuned again for this convention, from the drop-mode
         # point (the rest of the schedule is kept).
         t = time.perf_counter()
-        if args.params or args.no_tune:
-            nd_params = params
-        else:
+        if tune_nd:
             nd_tuner = autotune.Autotuner(progress=log, budget_s=NO_DROP_TUNE_BUDGET_S)
             nd_params = nd_tuner.tune_single(w.design, job.d, job.g, fl_nd, pr, w.T, drop=False, start=params,
                                              names=NO_DROP_TUNED)
+        else:
+            nd_params = params
         nd_tune_s = time.perf_counter() - t
-        kw = autotune.single_kwargs(nd_params, pr)
-        for _ in range(2):   # the first run also loads code objects
-            ndet, nev, _ = riros.fault_sim(job.d, job.g, fl_nd, mode=riros.MODE_TWO_D, drop=False,
-                                           priority=pr, **kw)
-            nd_ms = riros.last_kernel_ms()
+        ndet, nev, nd_ms = nd_run(idx, nd_params)
         FT = n * w.T
         nodrop = {"sample_faults": n, "nominal_fault_cycles_per_s": FT / (nd_ms * 1e-3), "fault_cycles": FT,
                   "kernel_ms": nd_ms, "events": int(nev.sum()),
                   "detect_identical": bool(np.array_equal(ndet, best["detect"][0][idx])),
-                  "params": nd_params, "tune_s": nd_tune_s}
+                  "params": nd_params, "tune_s": nd_tune_s,
+                  "probe": {"faults": int(probe.size), "kernel_ms": probe_ms}}
         log(f"[bench] no-drop sample of {n}: kernel {nd_ms:.3f} ms, {nodrop['nominal_fault_cycles_per_s']:.4g} F*T/s, "
             f"params {nd_params} (tuned in {nd_tune_s:.1f}s)")
 
