@@ -107,6 +107,17 @@ def measured_traffic(workload):
     return float(fields["hbm_bytes_per_pass"])
 
 
+def no_drop_sample(F, probe_n, probe_ms):
+    """Faults of the no-dropping leg and whether to tune it: the full sample
+    (NO_DROP_SAMPLE faults, or the whole list if shorter), tuned, unless its
+    pass, extrapolated from the probe's, would exceed NO_DROP_MAX_MS; then the
+    probe's faults, untuned."""
+    n = min(F, NO_DROP_SAMPLE)
+    if probe_n <= 0 or probe_ms * n / probe_n > NO_DROP_MAX_MS:
+        return probe_n, False
+    return n, True
+
+
 COPY_BYTES = 1 << 30
 
 
@@ -513,10 +524,8 @@ def main():
         # the whole sample would take too long the leg keeps those, untuned.
         probe = np.sort(rank[:min(w.faults.size, NO_DROP_PROBE)])
         _, _, probe_ms = nd_run(probe, params)
-        n = min(w.faults.size, NO_DROP_SAMPLE)
-        tune_nd = not (args.params or args.no_tune)
-        if probe_ms * n / probe.size > NO_DROP_MAX_MS:
-            n, tune_nd = probe.size, False
+        n, tune_nd = no_drop_sample(w.faults.size, probe.size, probe_ms)
+        tune_nd = tune_nd and not (args.params or args.no_tune)
         idx = np.sort(rank[:n])
         pr = None if preds is None else np.ascontiguousarray(preds[idx], np.float32)
         fl_nd = np.ascontiguousarray(w.faults[idx])
