@@ -43,6 +43,26 @@ def single(name: str):
     return _CACHE[name]
 
 
+def no_drop_sample(name: str, n: int):
+    """(workload restricted to the sample, detect, events, words) without
+    dropping, on the seeded sample of n faults the benchmark's no-dropping
+    leg draws (the n first of a counter-stream ranking, in list order)."""
+    key = ("nodrop", name, n)
+    if key not in _CACHE:
+        t = time.time()
+        w = {"heavy_tailed": W.heavy_tailed, "large": W.large}[name]()
+        rank = np.argsort(W.counter_values(0xD0D0, 0, w.faults.size), kind="stable")
+        idx = np.sort(rank[:min(n, w.faults.size)])
+        ws = W.Workload(w.name, w.design, w.stimulus, np.ascontiguousarray(w.faults[idx]), w.T)
+        G = oracle.golden(ws.design, ws.stimulus, ws.T)
+        det, ev, words, _ = oracle.fault_sim_stats(ws.design, ws.stimulus, ws.T, ws.faults, G=G, drop=False,
+                                                   nthreads=oracle.default_threads())
+        del G
+        _log(f"[oracle] {name} without dropping: {ws.faults.size} faults in {time.time() - t:.1f}s")
+        _CACHE[key] = (ws, det, ev, words)
+    return _CACHE[key]
+
+
 def campaign():
     """[(workload, detect, events, words)] for the 64 designs of the campaign."""
     if "campaign" not in _CACHE:

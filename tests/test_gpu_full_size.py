@@ -1,7 +1,8 @@
 """Full-size parity: every fault of the heavy-tailed (200,000 faults, 5,000
 cycles), large (1,000,000 faults, 10,000 cycles) and batched-campaign (64
 designs) workloads against the oracle, bit-exact: detect cycle, event count
-and byte-model words of each fault, and the coverage totals.
+and byte-model words of each fault, and the coverage totals; and the large
+workload's no-dropping sample (20,000 faults for all 10,000 cycles).
 
 The oracle runs on the host in the same process (tests/full_size_ref.py).
 The GPU runs use the benchmark's kind of launch: two-dimensional mode with
@@ -77,9 +78,41 @@ def test_full_size_every_fault(name):
     opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio, light_cap=4, waves_per_cu=12,
                            unified=1, struct_share=4, lockstep=1, deal=8)
     _compare(name + " two-dimensional (lockstep, dealt)", w, *_device_run(d, g, w, opts), odet, oev, owk)
+    # The schedules the tuner picks since head batches of 64 joined its
+    # space: free-running lanes, head batches filling all 64 lanes, with the
+    # monitor at 4 and no structural work in launch A, or the unified
+    # schedule with the monitor off and workspaces shared by four.
+    for kw in ({"unified": 0, "monitor_rate": 4.0, "waves_per_cu": 8, "struct_share": 2},
+               {"unified": 1, "monitor_rate": 0.0, "waves_per_cu": 16, "struct_share": 4}):
+        print(f"[full-size] {name}: head batches of 64, {kw}", flush=True)
+        opts = riros.make_opts(riros.MODE_TWO_D, True, True, stream=s, priority=prio, light_cap=4, heavy_wg=64,
+                               lockstep=0, head_lanes=64, **kw)
+        _compare(name + f" two-dimensional (head batches of 64, {kw})", w, *_device_run(d, g, w, opts),
+                 odet, oev, owk)
     print(f"[full-size] {name}: plain", flush=True)
     _compare(name + " plain", w, *_device_run(d, g, w, riros.make_opts(riros.MODE_PLAIN, True, True, stream=s)),
              odet, oev, owk)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_no_drop_sample():
+    """The benchmark's no-dropping leg: its 20,000-fault sample of the large
+    workload, every fault simulated for all 10,000 cycles, against the
+    oracle without dropping, under the drop-mode schedule and the one its
+    no-dropping tuning picks (capacity 8, the monitor off, unified)."""
+    w, odet, oev, owk = ref.no_drop_sample("large", 20000)
+    print(f"[full-size] large without dropping: F={w.faults.size}", flush=True)
+    d = riros.Design(w.design)
+    g = riros.Golden(d, w.stimulus, w.T)
+    pred = _priorities(d, g, w)
+    prio = torch.from_numpy(np.ascontiguousarray(pred, np.float32)).cuda()
+    s = torch.cuda.current_stream()
+    base = {"heavy_wg": 64, "lockstep": 0, "head_lanes": 64, "waves_per_cu": 12}
+    for kw in ({"light_cap": 4, "unified": 0, "monitor_rate": 4.0, "struct_share": 2},
+               {"light_cap": 8, "unified": 1, "monitor_rate": 0.0, "struct_share": 4}):
+        print(f"[full-size] large without dropping: {kw}", flush=True)
+        opts = riros.make_opts(riros.MODE_TWO_D, False, True, stream=s, priority=prio, **base, **kw)
+        _compare(f"large without dropping ({kw})", w, *_device_run(d, g, w, opts), odet, oev, owk)
 
 
 @pytest.mark.timeout(600)
