@@ -50,9 +50,12 @@ OPS_PER_EVENT = 10
 OPS_PER_FC = 3
 NO_DROP_SAMPLE = 20000     # faults of the no-dropping leg (seeded draw)
 NO_DROP_PROBE = 2000       # its first faults, timed first to bound the leg
-NO_DROP_MAX_MS = 3000.0    # a pass of the full sample longer than this keeps the probe, untuned
+NO_DROP_MAX_MS = 3000.0    # a pass of the full sample longer than this keeps the probe
+NO_DROP_PROBE_TUNE_MS = 2000.0   # the probe is tuned when its pass takes at most this
 NO_DROP_TUNE_BUDGET_S = 20.0
-NO_DROP_TUNED = ("light_cap", "monitor_rate", "unified")
+# in the order descended: the two that move the most first, so that a design
+# whose candidates take seconds reaches them within the budget
+NO_DROP_TUNED = ("light_cap", "heavy_wg", "unified", "monitor_rate")
 TRAIN_EPOCHS = 30
 PLAIN_STEPS = 2          # the plain kernel is timed on at most this many steps
 TUNE_BUDGET_S = 45.0
@@ -111,10 +114,11 @@ def no_drop_sample(F, probe_n, probe_ms):
     """Faults of the no-dropping leg and whether to tune it: the full sample
     (NO_DROP_SAMPLE faults, or the whole list if shorter), tuned, unless its
     pass, extrapolated from the probe's, would exceed NO_DROP_MAX_MS; then the
-    probe's faults, untuned."""
+    probe's faults, tuned only if a probe pass takes at most
+    NO_DROP_PROBE_TUNE_MS (each candidate is timed three times)."""
     n = min(F, NO_DROP_SAMPLE)
     if probe_n <= 0 or probe_ms * n / probe_n > NO_DROP_MAX_MS:
-        return probe_n, False
+        return probe_n, probe_n > 0 and probe_ms <= NO_DROP_PROBE_TUNE_MS
     return n, True
 
 
@@ -521,7 +525,8 @@ def main():
         # A design whose detected faults keep diverging across most of it
         # every cycle (no dropping) can take seconds per thousand faults: the
         # drop-mode schedule is timed on the sample's first faults, and when
-        # the whole sample would take too long the leg keeps those, untuned.
+        # the whole sample would take too long the leg keeps those (tuned
+        # when a pass over them is short enough).
         probe = np.sort(rank[:min(w.faults.size, NO_DROP_PROBE)])
         _, _, probe_ms = nd_run(probe, params)
         n, tune_nd = no_drop_sample(w.faults.size, probe.size, probe_ms)
@@ -531,9 +536,10 @@ def main():
         fl_nd = np.ascontiguousarray(w.faults[idx])
         # Without dropping, a detected fault keeps diverging for every
         # remaining cycle, so more of them outgrow a lane and run whole on the
-        # structural path: the lane capacity, the monitor and the unified
-        # schedule are tuned again for this convention, from the drop-mode
-        # point (the rest of the schedule is kept).
+        # structural path: the lane capacity, the monitor, the unified
+        # schedule and the structural workgroup size are tuned again for this
+        # convention, from the drop-mode point (the rest of the schedule is
+        # kept).
         t = time.perf_counter()
         if tune_nd:
             nd_tuner = autotune.Autotuner(progress=log, budget_s=NO_DROP_TUNE_BUDGET_S)

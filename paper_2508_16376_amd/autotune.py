@@ -57,7 +57,7 @@ SPACE = {
 # for the head batch, how many heavy faults there are to spread; for the
 # monitor, how many faults reach the structural path, which pays together
 # with the unified schedule or not at all).
-SCALE_PARAMS = ("monitor_rate", "waves_per_cu", "struct_share", "heavy_wg", "lockstep", "unified", "head_lanes")
+SCALE_PARAMS = ("monitor_rate", "lockstep", "unified", "waves_per_cu", "struct_share", "heavy_wg", "head_lanes")
 # Parameters that pay only together with another's value: the unified
 # schedule needs workspaces shared by several wavefronts (one workspace per
 # wavefront holds too few of them resident), so each unified value is tried
@@ -121,7 +121,8 @@ class Autotuner:
 
     def _descend(self, measure, with_priority: bool, confirm: int = 3, start=None, names=None, values=None):
         """Coordinate descent from ``start`` (default DEFAULT) over the
-        parameters in ``names`` (default every one of SPACE), with the
+        parameters in ``names``, in that order (default every one of SPACE,
+        in SPACE's order), with the
         candidate values of ``values`` where it names a parameter (default
         SPACE's).  A parameter of JOINT is tried with every value of its
         partner when the partner is descended too."""
@@ -140,8 +141,9 @@ class Autotuner:
         # the structural path); the second pass only times unseen points.
         for _ in range(2):
             start = dict(best)
-            for name, space_values in SPACE.items():
-                if (name == "heavy_quantile" and not with_priority) or (names is not None and name not in names):
+            for name in (SPACE if names is None else names):
+                space_values = SPACE[name]
+                if name == "heavy_quantile" and not with_priority:
                     continue
                 vals = (values or {}).get(name, space_values)
                 partner = JOINT.get(name)

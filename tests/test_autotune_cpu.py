@@ -169,3 +169,19 @@ def test_whole_list_values_replace_the_space():
     autotune.Autotuner()._descend(cost, with_priority=False, start=start, names=("monitor_rate",),
                                   values=autotune.WHOLE_LIST_VALUES)
     assert set(timed) <= set(autotune.WHOLE_LIST_VALUES["monitor_rate"])
+
+
+def test_named_descent_follows_the_given_order():
+    """A restricted descent visits its parameters in the order given."""
+    first_seen = []
+
+    def cost(p):
+        for k in ("heavy_wg", "light_cap", "unified", "monitor_rate"):
+            if p[k] != start[k] and k not in first_seen:
+                first_seen.append(k)
+        return 1.0
+
+    start = dict(autotune.DEFAULT)
+    autotune.Autotuner()._descend(cost, with_priority=False, start=start,
+                                  names=("light_cap", "heavy_wg", "unified", "monitor_rate"))
+    assert first_seen == ["light_cap", "heavy_wg", "unified", "monitor_rate"]

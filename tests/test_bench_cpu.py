@@ -43,7 +43,9 @@ def test_more_than_one_gpu_is_refused():
 def test_no_drop_sample_keeps_the_probe_when_the_full_sample_is_too_slow():
     # large: 2,000 faults in 127 ms -> 20,000 in about 1.3 s, tuned
     assert bench.no_drop_sample(1_000_000, 2000, 127.0) == (bench.NO_DROP_SAMPLE, True)
-    # medium: 2,000 faults in 1,193 ms -> about 12 s: the probe, untuned
-    assert bench.no_drop_sample(50_000, 2000, 1193.0) == (2000, False)
+    # medium: 2,000 faults in 1,193 ms -> about 12 s: the probe, tuned
+    assert bench.no_drop_sample(50_000, 2000, 1193.0) == (2000, True)
+    # a probe pass of several seconds: the probe, untuned
+    assert bench.no_drop_sample(50_000, 2000, 5000.0) == (2000, False)
     # a list shorter than the sample: the whole list
     assert bench.no_drop_sample(1500, 1500, 5.0) == (1500, True)
